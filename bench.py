@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the DG acoustics hot path on one MI355X.
+
+One bench step is one LSRK(5,4) time step: five stages, each a full
+right-hand side (trace, volume, surface + lift, inverse mass) and the RK
+update, over every element of the mesh.  Default workload: the unit cube as
+40^3 perturbed hexahedra x 6 = 384 000 pyramids, N = 4 (Np = 55), four fields,
+c = 1, wall boundaries, penalty flux; synthetic seeded mesh and state.
+
+Prints one JSON line.  ``value`` is GDOF.stages/s = 4 Np K * 5 * steps / t.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GDOF·stages/s, FP64 plain vs FP32-MFMA form at equal L2 error, N=3–7"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def n_basis(N):
+    return (N + 1) * (N + 2) * (2 * N + 3) // 6
+
+
+def kernel_work(name: str, N: int):
+    """Algorithmic flops and HBM bytes per element for one launch of a kernel.
+
+    Flops count what the method computes (dense operators of Algorithms 1-3);
+    bytes count the FP64 data the method must move through HBM (state in and
+    out, quad-base traces, 15 vertex doubles, neighbour ids and material).
+    """
+    Np, n1 = n_basis(N), N + 1
+    Nc, Nfc, Nab = n1 ** 3, 5 * n1 ** 2, n1 ** 2
+    if name == "trace":            # U^f = V^f U on every face, 4 fields
+        return 8 * Nfc * Np, 32 * Np + 32 * Nab
+    if name == "volume":           # [Dr;Ds;Dt] U, pointwise metric, V^T (W .)
+        return 32 * Nc * Np + 40 * Nc, 32 * Np + 32 * Np + 120
+    if name == "surface_update":   # flux, LIFT, inverse mass, LSRK
+        return 8 * Nfc * Np + 25 * Nfc + 24 * Np, 32 * Np * 5 + 32 * Nab + 152
+    raise KeyError(name)
+
+
+def stage_work(N: int):
+    """Whole-stage algorithmic flops and bytes per element."""
+    Np, n1 = n_basis(N), N + 1
+    Nc, Nfc, Nab = n1 ** 3, 5 * n1 ** 2, n1 ** 2
+    F = 32 * Nc * Np + 16 * Nfc * Np + 40 * Nc + 25 * Nfc + 24 * Np
+    B = 128 * Np + 64 * Nab + 152
+    return F, B
+
+
+def cpu_baseline(xyz, e2v, N, U, nsample, reps=3):
+    """The oracle's right-hand side on a seeded sample of elements, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import AcousticDG
+    K = e2v.shape[0]
+    rng = np.random.default_rng(2024)
+    S = np.sort(rng.choice(K, min(nsample, K), replace=False))
+    o = AcousticDG(xyz, e2v, N, elems=S)
+    times = []
+    with threadpool_limits(1):
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            o.rhs(U)
+            times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    rate = 4 * n_basis(N) * S.size / t / 1e9
+    return {"value": rate, "unit": "GDOF·stages/s", "cores": 1, "kind": "oracle",
+            "sample": f"{S.size} of {K} elements, one right-hand side (= one stage), median of "
+                      f"{reps}, BLAS limited to 1 thread, host {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--k1d", type=int, default=40)
+    ap.add_argument("--N", type=int, default=4)
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
+              "single-device and is not sharded across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1502_07703_amd as dg
+    from synth import hex_pyramid_mesh, random_state
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    N = args.N
+    Np = n_basis(N)
+    xyz, e2v = hex_pyramid_mesh(args.k1d, seed=2)
+    K = e2v.shape[0]
+    Uh = random_state(K, N, seed=11, scale=1e-3)
+    solver = dg.Solver(xyz, e2v, N, precision=args.precision)
+    U = solver.pack(torch.from_numpy(Uh).cuda())
+    R = solver.empty_state().zero_()
+    dt = solver.stable_dt(0.5)
+    stream = torch.cuda.current_stream()
+
+    solver.step(U, R, dt, args.warmup)
+    torch.cuda.synchronize()
+
+    names = dg._binding.lib().dgpyr_kernel_names(solver._h).decode().split(";")
+    import ctypes
+    nk = len(names)
+    ms = (ctypes.c_double * nk)()
+    cnt = (ctypes.c_int64 * nk)()
+
+    # Timed region: K steps, each kernel launch bracketed by HIP events on the
+    # launch stream; wall time bracketed by synchronisation.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = dg._binding.lib().dgpyr_step_timed(solver._h, ctypes.c_void_p(U.data_ptr()),
+                                            ctypes.c_void_p(R.data_ptr()), 0.0, dt, args.steps,
+                                            ctypes.c_void_p(stream.cuda_stream), nk, ms, cnt)
+    dg._binding.check(st, "dgpyr_step_timed")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if not torch.isfinite(U).all():
+        print("non-finite state after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    stages = 5 * args.steps
+    value = 4 * Np * K * stages / wall / 1e9
+    kernels = {}
+    for i, nm in enumerate(names):
+        avg = ms[i] / max(cnt[i], 1)
+        F, Bb = kernel_work(nm, N)
+        kernels[nm] = {"avg_ms": avg, "launches": int(cnt[i]),
+                       "tflops": F * K / (avg * 1e-3) / 1e12,
+                       "gbs": Bb * K / (avg * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    Fd, Bd = kernel_work(dom, N)
+    t_d = kernels[dom]["avg_ms"] * 1e-3
+    compute_bound = Fd / (PEAK_FP64_TFLOPS * 1e12) >= Bd / (PEAK_HBM_GBS * 1e9)
+    if compute_bound:
+        ach = Fd * K / t_d / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
+    else:
+        ach = Bd * K / t_d / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
+                "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
+    Fs, Bs = stage_work(N)
+    t_stage = wall / stages
+    whole = {"flop_per_stage": Fs * K, "bytes_per_stage": Bs * K,
+             "tflops": Fs * K / t_stage / 1e12, "gbs": Bs * K / t_stage / 1e9,
+             "frac_fp64_roof": (Fs * K / t_stage) / (PEAK_FP64_TFLOPS * 1e12),
+             "frac_hbm_roof": (Bs * K / t_stage) / (PEAK_HBM_GBS * 1e9)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GDOF·stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"unit cube, {args.k1d}^3 perturbed hexes x 6 = {K} pyramids, "
+                               f"N={N}, 4 fields, walls, penalty flux, LSRK(5,4)",
+                   "k1d": args.k1d, "nelems": K, "N": N, "Np": Np, "dof": 4 * Np * K,
+                   "precision": args.precision, "stages_per_step": 5, "dt": dt},
+        "roofline": roof,
+        "stage": whole,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(xyz, e2v, N, Uh, args.cpu_sample)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * dgpyr -- time-explicit DG for first-order linear acoustics on meshes of
+ * vertex-mapped pyramids, with the semi-nodal orthogonal basis of
+ * Chan & Warburton, "Orthogonal bases for vertex-mapped pyramids" (Lemma 3).
+ *
+ * C ABI.  Every call returns a dgpyr_status (0 = success, < 0 = error) and never
+ * aborts or throws; on failure a thread-local message is available from
+ * dgpyr_last_error().  Device pointers are HIP device addresses; streams are
+ * hipStream_t handles passed as void* (NULL = the null stream).
+ *
+ * Method (Section 4.3): for piecewise-constant density rho and bulk modulus
+ * kappa the semi-discrete system is
+ *   dp/dt   = -kappa M^-1 ( sum_k S^k u_k + L^f P_p )
+ *   du_k/dt = -(1/rho) M^-1 ( S^k p + L^{f,k} P_u ),
+ * with S^k the strong derivative matrices (Algorithm 1), L^f, L^{f,k} the
+ * surface lifts of the penalty terms P_p = 1/2 (n.[[u]] - tau_p [[p]]) and
+ * P_u = 1/2 ([[p]] - tau_u n.[[u]]) (Algorithm 2), [[q]] = q+ - q-,
+ * tau_p = alpha / {rho c}, tau_u = alpha {rho c}, {.} the arithmetic mean, and
+ * M the mass matrix, diagonal in the semi-nodal basis (Lemma 3).  Time
+ * integration is the low-storage RK(5,4) of Carpenter and Kennedy
+ * (Section 4.1, Algorithm 3).
+ */
+#ifndef DGPYR_H
+#define DGPYR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DGPYR_OK = 0,
+  DGPYR_E_ARG = -1,            /* null pointer, bad size or bad option            */
+  DGPYR_E_ORDER = -2,          /* N outside [0, DGPYR_MAX_ORDER]                   */
+  DGPYR_E_MESH = -3,           /* degenerate or inverted pyramid (J <= 0)          */
+  DGPYR_E_NONCONFORMING = -4,  /* a face is shared by more than two elements, or
+                                  the two sides' face points do not coincide       */
+  DGPYR_E_HIP = -5,            /* a HIP runtime call failed                        */
+  DGPYR_E_OOM = -6,            /* device allocation failed                         */
+  DGPYR_E_STATE = -7,          /* context not usable for this call                 */
+  DGPYR_E_UNSUPPORTED = -8     /* option combination not built                     */
+} dgpyr_status;
+
+#define DGPYR_MAX_ORDER 8
+
+typedef enum {
+  DGPYR_BC_WALL = 0, /* rigid wall n.u = 0: mirror p+ = p-, u+ = u- - 2 (n.u-) n */
+  DGPYR_BC_FREE = 1  /* free surface p = 0: mirror p+ = -p-, u+ = u-            */
+} dgpyr_bc;
+
+typedef enum {
+  DGPYR_FP64 = 0,      /* every step in FP64                                         */
+  DGPYR_FP32_MFMA = 1, /* volume and lift contractions in FP32 on the matrix cores
+                          with FP32 accumulation; geometry, traces, flux, inverse
+                          mass and RK state in FP64                                  */
+  DGPYR_SPLIT_BF16 = 2 /* as FP32_MFMA, operators split into bf16 hi + lo parts      */
+} dgpyr_precision;
+
+/* Mesh, read on the host during dgpyr_setup only (the caller keeps ownership).
+ * Element e has vertices e2v[5e .. 5e+4] = (v0, v1, v2, v3, v4): v0..v3 is the
+ * base, counter-clockwise seen from the apex v4, i.e.
+ * ((x1 - x0) x (x3 - x0)) . (x4 - x0) > 0.  In collapsed coordinates
+ * (Section 2) v0 sits at (a, b) = (-1, -1), v1 at (1, -1), v2 at (1, 1),
+ * v3 at (-1, 1); the vertex map is x = (1-c)/2 B(a, b) + (1+c)/2 x4 with B the
+ * bilinear interpolant of the base, which equals the map built from
+ * Bedrosian's vertex functions. */
+typedef struct {
+  int64_t nverts;
+  const double* xyz;    /* [nverts][3]                                            */
+  int64_t nelems;
+  const int64_t* e2v;   /* [nelems][5], entries in [0, nverts)                    */
+  const double* rho;    /* [nelems] density, or NULL for 1                         */
+  const double* kappa;  /* [nelems] bulk modulus, or NULL for 1                    */
+  int32_t bc;           /* dgpyr_bc, applied on every face without a neighbour    */
+} dgpyr_mesh;
+
+typedef struct {
+  int32_t precision; /* dgpyr_precision                                           */
+  double alpha;      /* penalty scale: 0 = central flux, 1 = the flux of 4.3      */
+  uint32_t flags;    /* reserved, must be 0                                       */
+} dgpyr_opts;
+
+typedef struct {
+  int32_t N;               /* polynomial degree                                    */
+  int32_t Np;              /* basis functions per element (N+1)(N+2)(2N+3)/6       */
+  int32_t Nc;              /* volume cubature points (N+1)^3                       */
+  int32_t Nfc;             /* surface cubature points 5 (N+1)^2                    */
+  int64_t nelems;          /* K                                                    */
+  int64_t state_len;       /* doubles in one state array (U, R or dU/dt)           */
+  int64_t canon_len;       /* doubles in the canonical array, K * 4 * Np           */
+  double inv_length_max;   /* max over elements of c_K |dK| / |K|                  */
+  int32_t hex_groups;      /* 1 if elements come in groups of 6 sharing an apex    */
+  int32_t precision;       /* precision form built                                 */
+  int64_t device_bytes;    /* device memory held by the context                    */
+} dgpyr_info;
+
+typedef struct dgpyr_ctx dgpyr_ctx;
+
+/* Build reference rules, basis and operators on the host in FP64 (Lemma 3,
+ * Section 4.1 minimal rule), per-element geometry and face connectivity, and
+ * upload them to the current HIP device.  Synchronous.  On failure *out is
+ * set to NULL.  Errors: E_ARG (null pointers, bad bc/precision/flags),
+ * E_ORDER, E_MESH (J <= 0 at a base corner or degenerate vertex map),
+ * E_NONCONFORMING, E_UNSUPPORTED, E_OOM, E_HIP. */
+dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts,
+                         void* stream, dgpyr_ctx** out);
+
+/* Sizes and derived quantities of a context. */
+dgpyr_status dgpyr_get_info(const dgpyr_ctx* ctx, dgpyr_info* info);
+
+/* Convert between the canonical layout and the library's state layout.
+ * Canonical: [K][4][Np], fields p, u, v, w; basis index
+ * n(i, j, k) = k(k+1)(2k+1)/6 + j(k+1) + i for phi_ijk of Lemma 3 with the
+ * Jacobi factor in its standard normalisation.  Both pointers are device
+ * arrays of canon_len and state_len doubles; asynchronous on the stream. */
+dgpyr_status dgpyr_pack(dgpyr_ctx* ctx, const double* canon, double* U, void* stream);
+dgpyr_status dgpyr_unpack(dgpyr_ctx* ctx, const double* U, double* canon, void* stream);
+
+/* dUdt = full semi-discrete right-hand side of Section 4.3 at state U
+ * (inverse mass and material factors included).  U and dUdt are device state
+ * arrays (may not alias).  t is accepted for source terms and is unused here.
+ * Asynchronous on the stream. */
+dgpyr_status dgpyr_rhs(dgpyr_ctx* ctx, const double* U, double* dUdt, double t, void* stream);
+
+/* nsteps LSRK(5,4) steps of size dt (Algorithm 3): per stage
+ * R <- A_s R + dt rhs(U), U <- U + B_s R.  U and R are device state arrays,
+ * updated in place; R need not be initialised (A_1 = 0).  Asynchronous. */
+dgpyr_status dgpyr_step(dgpyr_ctx* ctx, double* U, double* R, double t0, double dt,
+                        int32_t nsteps, void* stream);
+
+/* As dgpyr_step, and also times every kernel launch with HIP events recorded
+ * on the stream around it.  kernel_ms[k] receives the summed milliseconds and
+ * launches[k] the launch count of kernel kind k, for k < nk (kinds are named by
+ * dgpyr_kernel_names).  Returns after the work has completed (synchronises
+ * the stream).  For measurement; the numerical result equals dgpyr_step's. */
+dgpyr_status dgpyr_step_timed(dgpyr_ctx* ctx, double* U, double* R, double t0, double dt,
+                              int32_t nsteps, void* stream, int32_t nk, double* kernel_ms,
+                              int64_t* launches);
+
+/* Semicolon-separated names of the kernel kinds dgpyr_step launches, in the
+ * order used by dgpyr_step_timed; the string lives as long as the context. */
+const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
+
+/* Host-only inspection of the reference data the library builds for degree N
+ * (no device needed).  which: 0 volume weights [Nc]; 1 V [Nc][Np];
+ * 2 d/dr [Nc][Np]; 3 d/ds; 4 d/dt; 5 face basis values [Nfc][Np]; 6 face
+ * parameter weights [Nfc]; 7 reference mass diagonal [Np]; 8 volume points
+ * (a, b, c) [Nc][3]; 9 face points (a, b, c) [Nfc][3].  Writes min(len,
+ * needed) doubles to out (out may be NULL to query) and the full size to
+ * *needed.  Errors: E_ORDER, E_ARG. */
+dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,
+                                  int64_t* needed);
+
+/* Host-only run of the mesh builders (geometry checks and face matching) that
+ * dgpyr_setup performs before touching the device.  nbr (optional, [nelems][5])
+ * receives the neighbour element of each face or -1; inv_length_max and
+ * hex_groups (optional) as in dgpyr_info.  Same errors as dgpyr_setup's host
+ * part. */
+dgpyr_status dgpyr_host_mesh(const dgpyr_mesh* mesh, int32_t N, int32_t* nbr,
+                             double* inv_length_max, int32_t* hex_groups);
+
+/* Release every device buffer of the context (synchronises the device first).
+ * NULL is accepted. */
+void dgpyr_destroy(dgpyr_ctx* ctx);
+
+const char* dgpyr_status_string(dgpyr_status s);
+const char* dgpyr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGPYR_H */

@@ -1,0 +1,140 @@
+"""dgpyr: DG acoustics on vertex-mapped pyramids for MI355X (gfx950).
+
+Python face of libdgpyr.so.  ``Solver`` marshals a pyramid mesh into
+``dgpyr_setup`` and calls ``dgpyr_rhs`` / ``dgpyr_step`` on torch device
+tensors and the current torch stream; all arithmetic runs in the library's
+HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import DgpyrError
+
+__all__ = ["Solver", "DgpyrError", "n_basis", "LSRK_CFL_CONSTANT"]
+
+
+def n_basis(N: int) -> int:
+    return (N + 1) * (N + 2) * (2 * N + 3) // 6
+
+
+def LSRK_CFL_CONSTANT(N: int) -> float:
+    """2(N+1)(N+3)/3, the constant the spectral radius tracks (Section 4.3)."""
+    return 2.0 * (N + 1) * (N + 3) / 3.0
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, length=None, name="array"):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if length is not None and t.numel() != length:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {length}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """A mesh and a discretisation set up on the current HIP device."""
+
+    def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
+                 precision="fp64", stream=None):
+        L = B.lib()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._e2v = np.ascontiguousarray(e2v, dtype=np.int64)
+        if self._xyz.ndim != 2 or self._xyz.shape[1] != 3:
+            raise ValueError("xyz must have shape (nverts, 3)")
+        if self._e2v.ndim != 2 or self._e2v.shape[1] != 5:
+            raise ValueError("e2v must have shape (nelems, 5)")
+        K = self._e2v.shape[0]
+        self._rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+        for a, nm in ((self._rho, "rho"), (self._kappa, "kappa")):
+            if a is not None and a.shape != (K,):
+                raise ValueError(f"{nm} must have shape ({K},)")
+        dptr = ctypes.POINTER(ctypes.c_double)
+        mesh = B.Mesh(
+            nverts=self._xyz.shape[0], xyz=self._xyz.ctypes.data_as(dptr),
+            nelems=K, e2v=self._e2v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            rho=None if self._rho is None else self._rho.ctypes.data_as(dptr),
+            kappa=None if self._kappa is None else self._kappa.ctypes.data_as(dptr),
+            bc=B.BC[bc])
+        opts = B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=0)
+        handle = ctypes.c_void_p()
+        st = L.dgpyr_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
+                           _stream_handle(stream) if stream is not None else None,
+                           ctypes.byref(handle))
+        B.check(st, "dgpyr_setup")
+        self._h = handle
+        info = B.Info()
+        B.check(L.dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
+        self.info = {k: getattr(info, k) for k, _ in B.Info._fields_}
+        self.N, self.Np, self.K = info.N, info.Np, info.nelems
+        self.state_len, self.canon_len = info.state_len, info.canon_len
+
+    # -- state helpers -----------------------------------------------------------
+    def empty_state(self):
+        import torch
+        return torch.empty(self.state_len, dtype=torch.float64, device="cuda")
+
+    def pack(self, canon, out=None, stream=None):
+        """Canonical (K, 4, Np) device tensor -> state array."""
+        out = self.empty_state() if out is None else out
+        B.check(B.lib().dgpyr_pack(self._h, _dptr(canon, self.canon_len, "canon"),
+                                   _dptr(out, self.state_len, "U"), _stream_handle(stream)),
+                "dgpyr_pack")
+        return out
+
+    def unpack(self, U, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.K, 4, self.Np), dtype=torch.float64, device="cuda")
+        B.check(B.lib().dgpyr_unpack(self._h, _dptr(U, self.state_len, "U"),
+                                     _dptr(out, self.canon_len, "canon"), _stream_handle(stream)),
+                "dgpyr_unpack")
+        return out
+
+    # -- the hot path ---------------------------------------------------------------
+    def rhs(self, U, out=None, t=0.0, stream=None):
+        out = self.empty_state() if out is None else out
+        B.check(B.lib().dgpyr_rhs(self._h, _dptr(U, self.state_len, "U"),
+                                  _dptr(out, self.state_len, "dUdt"), float(t),
+                                  _stream_handle(stream)), "dgpyr_rhs")
+        return out
+
+    def step(self, U, R, dt, nsteps=1, t0=0.0, stream=None):
+        B.check(B.lib().dgpyr_step(self._h, _dptr(U, self.state_len, "U"),
+                                   _dptr(R, self.state_len, "R"), float(t0), float(dt),
+                                   int(nsteps), _stream_handle(stream)), "dgpyr_step")
+        return U, R
+
+    def stable_dt(self, cfl=0.5):
+        """CFL / (2(N+1)(N+3)/3 * max_K c_K |dK|/|K|) (Section 4.3 scaling)."""
+        return cfl / (LSRK_CFL_CONSTANT(self.N) * self.info["inv_length_max"])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            B.lib().dgpyr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,413 @@
+// C ABI of the library: setup (host FP64 builders + upload), state layout,
+// right-hand side and LSRK stepping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "context.hpp"
+#include "dgpyr.h"
+#include "host/mesh.hpp"
+#include "host/refops.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+dgpyr_status fail(dgpyr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+dgpyr_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? DGPYR_E_OOM : DGPYR_E_HIP;
+}
+
+// Carpenter-Kennedy 2N-storage RK(5,4) coefficients.
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+template <typename T>
+dgpyr_status upload(dgpyr_ctx* c, const std::vector<T>& h, const T** out, const char* what) {
+  void* p = nullptr;
+  const size_t bytes = h.size() * sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 16);
+  if (e != hipSuccess) return hip_fail(e, what);
+  c->allocs.push_back(p);
+  c->device_bytes += (int64_t)bytes;
+  if (bytes) {
+    e = hipMemcpy(p, h.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+  }
+  *out = static_cast<const T*>(p);
+  return DGPYR_OK;
+}
+
+dgpyr_status alloc(dgpyr_ctx* c, size_t bytes, double** out, const char* what) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 16);
+  if (e != hipSuccess) return hip_fail(e, what);
+  c->allocs.push_back(p);
+  c->device_bytes += (int64_t)bytes;
+  *out = static_cast<double*>(p);
+  return DGPYR_OK;
+}
+
+std::vector<double> transpose(const std::vector<double>& A, int rows, int cols) {
+  std::vector<double> B((size_t)rows * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) B[(size_t)c * rows + r] = A[(size_t)r * cols + c];
+  return B;
+}
+
+// Times launches with a ring of HIP event pairs; the host only waits on an
+// event pair when it is about to reuse it, so it stays far ahead of the GPU.
+struct LaunchTimer {
+  static constexpr int kRing = 256;
+  hipStream_t s;
+  int nk;
+  double* ms;
+  int64_t* count;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  int64_t n = 0;
+  hipError_t err = hipSuccess;
+  LaunchTimer(hipStream_t s_, int nk_, double* ms_, int64_t* cnt_) : s(s_), nk(nk_), ms(ms_), count(cnt_) {
+    ev.resize(2 * kRing, nullptr);
+    kind.assign(kRing, -1);
+    for (auto& e : ev)
+      if (err == hipSuccess) err = hipEventCreate(&e);
+  }
+  ~LaunchTimer() {
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
+  }
+  void retire(int slot) {
+    if (kind[slot] < 0) return;
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(ev[2 * slot + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[2 * slot], ev[2 * slot + 1]);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    if (kind[slot] < nk) {
+      ms[kind[slot]] += t;
+      count[kind[slot]] += 1;
+    }
+    kind[slot] = -1;
+  }
+  void begin(int k) {
+    const int slot = (int)(n % kRing);
+    retire(slot);
+    kind[slot] = k;
+    hipError_t e = hipEventRecord(ev[2 * slot], s);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+  }
+  void end() {
+    const int slot = (int)(n % kRing);
+    hipError_t e = hipEventRecord(ev[2 * slot + 1], s);
+    if (e != hipSuccess && err == hipSuccess) err = e;
+    ++n;
+  }
+  void drain() {
+    for (int i = 0; i < kRing; ++i) retire(i);
+  }
+};
+
+const char* kKernelNames = "trace;volume;surface_update";
+
+// One LSRK stage (mode 1) or one right-hand side evaluation (mode 0).
+hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, double* R, double ra,
+                     double rb, double dt, hipStream_t s, LaunchTimer* tm) {
+  if (tm) tm->begin(0);
+  hipError_t e = dgpyr::launch_trace(*c, U, c->T, s);
+  if (tm) tm->end();
+  if (e != hipSuccess) return e;
+  if (tm) tm->begin(1);
+  e = dgpyr::launch_volume(*c, U, c->vol, s);
+  if (tm) tm->end();
+  if (e != hipSuccess) return e;
+  if (tm) tm->begin(2);
+  e = dgpyr::launch_surface(*c, mode, c->T, c->vol, out, R, ra, rb, dt, s);
+  if (tm) tm->end();
+  return e;
+}
+
+void free_ctx(dgpyr_ctx* c) {
+  if (!c) return;
+  for (void* p : c->allocs) hipFree(p);
+  delete c;
+}
+
+dgpyr_status check_ctx(const dgpyr_ctx* c) {
+  if (!c) return fail(DGPYR_E_ARG, "null context");
+  return DGPYR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dgpyr_status_string(dgpyr_status s) {
+  switch (s) {
+    case DGPYR_OK: return "ok";
+    case DGPYR_E_ARG: return "invalid argument";
+    case DGPYR_E_ORDER: return "polynomial degree out of range";
+    case DGPYR_E_MESH: return "invalid mesh geometry";
+    case DGPYR_E_NONCONFORMING: return "non-conforming mesh";
+    case DGPYR_E_HIP: return "HIP runtime error";
+    case DGPYR_E_OOM: return "out of device memory";
+    case DGPYR_E_STATE: return "invalid context state";
+    case DGPYR_E_UNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+const char* dgpyr_last_error(void) { return g_err.c_str(); }
+
+dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts, void* stream,
+                         dgpyr_ctx** out) {
+  (void)stream;
+  if (!out) return fail(DGPYR_E_ARG, "out is null");
+  *out = nullptr;
+  if (!mesh || !opts) return fail(DGPYR_E_ARG, "mesh or opts is null");
+  if (!mesh->xyz || !mesh->e2v || mesh->nverts <= 0 || mesh->nelems <= 0)
+    return fail(DGPYR_E_ARG, "mesh arrays must be non-null with positive sizes");
+  if (mesh->nelems > (int64_t)0x7fffffff) return fail(DGPYR_E_ARG, "more than 2^31-1 elements");
+  if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
+  if (mesh->bc != DGPYR_BC_WALL && mesh->bc != DGPYR_BC_FREE) return fail(DGPYR_E_ARG, "bad bc");
+  if (opts->flags != 0) return fail(DGPYR_E_ARG, "flags must be 0");
+  if (!(opts->alpha >= 0.0)) return fail(DGPYR_E_ARG, "alpha must be >= 0");
+  if (opts->precision != DGPYR_FP64)
+    return fail(DGPYR_E_UNSUPPORTED, "only the FP64 form is built in this library");
+
+  dgpyr_ctx* c = new (std::nothrow) dgpyr_ctx();
+  if (!c) return fail(DGPYR_E_OOM, "host allocation failed");
+  char msg[256];
+  dgpyr::RefOps ops;
+  if (!dgpyr::build_refops(N, ops, msg, sizeof msg)) {
+    free_ctx(c);
+    return fail(DGPYR_E_STATE, msg);
+  }
+  dgpyr::MeshData md;
+  std::string err;
+  int rc = dgpyr::build_mesh(ops, mesh->nverts, mesh->xyz, mesh->nelems, mesh->e2v, mesh->rho,
+                             mesh->kappa, md, err);
+  if (rc != 0) {
+    free_ctx(c);
+    return fail((dgpyr_status)rc, err);
+  }
+  c->N = N;
+  c->Np = ops.Np;
+  c->Nc = ops.Nc;
+  c->Nfq = ops.Nfq;
+  c->Nfc = ops.Nfc;
+  c->K = mesh->nelems;
+  c->precision = opts->precision;
+  c->bc = mesh->bc;
+  c->alpha = opts->alpha;
+  c->inv_length_max = md.inv_length_max;
+  c->hex_groups = md.hex_groups;
+
+  std::vector<int> perm((size_t)10 * ops.Nfq);
+  for (int o = 0; o < 8; ++o) dgpyr::quad_perm(N, o, &perm[(size_t)o * ops.Nfq]);
+  for (int o = 0; o < 2; ++o) dgpyr::tri_perm(N, o, &perm[(size_t)(8 + o) * ops.Nfq]);
+
+  dgpyr_status st = DGPYR_OK;
+#define UP(vec, field) \
+  if (st == DGPYR_OK) st = upload(c, vec, &c->ops.field, #field);
+  UP(transpose(ops.Dr, ops.Nc, ops.Np), DrT)
+  UP(transpose(ops.Ds, ops.Nc, ops.Np), DsT)
+  UP(transpose(ops.Dt, ops.Nc, ops.Np), DtT)
+  UP(ops.V, V)
+  UP(transpose(ops.Vf, ops.Nfc, ops.Np), VfT)
+  UP(ops.Vf, Vf)
+  UP(ops.wv, wv)
+  UP(ops.wf, wf)
+  UP(ops.fa, fa)
+  UP(ops.fb, fb)
+  UP(ops.xg, xg)
+  UP(ops.na, na)
+  UP(ops.nb, nb)
+  UP(ops.wwc, wwc)
+  UP(perm, perm)
+#undef UP
+  if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
+  if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
+  if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
+  if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->T, "trace buffer");
+  if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->vol, "volume buffer");
+  if (st != DGPYR_OK) {
+    free_ctx(c);
+    return st;
+  }
+  c->mesh.K = c->K;
+  c->mesh.bc = c->bc;
+  c->mesh.alpha = c->alpha;
+  *out = c;
+  return DGPYR_OK;
+}
+
+dgpyr_status dgpyr_get_info(const dgpyr_ctx* c, dgpyr_info* info) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!info) return fail(DGPYR_E_ARG, "info is null");
+  info->N = c->N;
+  info->Np = c->Np;
+  info->Nc = c->Nc;
+  info->Nfc = c->Nfc;
+  info->nelems = c->K;
+  info->state_len = c->K * 4 * c->Np;
+  info->canon_len = c->K * 4 * c->Np;
+  info->inv_length_max = c->inv_length_max;
+  info->hex_groups = c->hex_groups ? 1 : 0;
+  info->precision = c->precision;
+  info->device_bytes = c->device_bytes;
+  return DGPYR_OK;
+}
+
+dgpyr_status dgpyr_pack(dgpyr_ctx* c, const double* canon, double* U, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!canon || !U) return fail(DGPYR_E_ARG, "null array");
+  hipError_t e = hipMemcpyAsync(U, canon, (size_t)c->K * 4 * c->Np * sizeof(double),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "pack");
+}
+
+dgpyr_status dgpyr_unpack(dgpyr_ctx* c, const double* U, double* canon, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!canon || !U) return fail(DGPYR_E_ARG, "null array");
+  hipError_t e = hipMemcpyAsync(canon, U, (size_t)c->K * 4 * c->Np * sizeof(double),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "unpack");
+}
+
+dgpyr_status dgpyr_rhs(dgpyr_ctx* c, const double* U, double* dUdt, double t, void* stream) {
+  (void)t;
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!U || !dUdt) return fail(DGPYR_E_ARG, "null array");
+  if ((const double*)dUdt == U) return fail(DGPYR_E_ARG, "U and dUdt must not alias");
+  hipError_t e = run_stage(c, 0, U, dUdt, nullptr, 0.0, 0.0, 0.0, (hipStream_t)stream, nullptr);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "rhs launch");
+}
+
+dgpyr_status dgpyr_step(dgpyr_ctx* c, double* U, double* R, double t0, double dt, int32_t nsteps,
+                        void* stream) {
+  (void)t0;
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!U || !R) return fail(DGPYR_E_ARG, "null array");
+  if (U == R) return fail(DGPYR_E_ARG, "U and R must not alias");
+  if (nsteps < 0) return fail(DGPYR_E_ARG, "nsteps must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  for (int n = 0; n < nsteps; ++n)
+    for (int st = 0; st < 5; ++st) {
+      hipError_t e = run_stage(c, 1, U, U, R, kRkA[st], kRkB[st], dt, s, nullptr);
+      if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+  return DGPYR_OK;
+}
+
+dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, double dt,
+                              int32_t nsteps, void* stream, int32_t nk, double* kernel_ms,
+                              int64_t* launches) {
+  (void)t0;
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!U || !R) return fail(DGPYR_E_ARG, "null array");
+  if (U == R) return fail(DGPYR_E_ARG, "U and R must not alias");
+  if (nsteps < 0 || nk < 0 || (nk > 0 && (!kernel_ms || !launches)))
+    return fail(DGPYR_E_ARG, "bad nsteps / timing arrays");
+  for (int k = 0; k < nk; ++k) {
+    kernel_ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  LaunchTimer tm(s, nk, kernel_ms, launches);
+  if (tm.err != hipSuccess) return hip_fail(tm.err, "event create");
+  for (int n = 0; n < nsteps; ++n)
+    for (int st = 0; st < 5; ++st) {
+      hipError_t e = run_stage(c, 1, U, U, R, kRkA[st], kRkB[st], dt, s, &tm);
+      if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+  tm.drain();
+  if (tm.err != hipSuccess) return hip_fail(tm.err, "event timing");
+  hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "stream synchronize");
+}
+
+const char* dgpyr_kernel_names(const dgpyr_ctx* c) {
+  (void)c;
+  return kKernelNames;
+}
+
+dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,
+                                  int64_t* needed) {
+  if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
+  if (!needed || len < 0) return fail(DGPYR_E_ARG, "needed is null or len < 0");
+  dgpyr::RefOps o;
+  char msg[256];
+  if (!dgpyr::build_refops(N, o, msg, sizeof msg)) return fail(DGPYR_E_STATE, msg);
+  std::vector<double> v;
+  switch (which) {
+    case 0: v = o.wv; break;
+    case 1: v = o.V; break;
+    case 2: v = o.Dr; break;
+    case 3: v = o.Ds; break;
+    case 4: v = o.Dt; break;
+    case 5: v = o.Vf; break;
+    case 6: v = o.wf; break;
+    case 7: v = o.wwc; break;
+    case 8:
+      for (int r = 0; r < o.Nq1; ++r)
+        for (int m = 0; m < o.Nq1; ++m)
+          for (int p = 0; p < o.Nq1; ++p) {
+            v.push_back(o.xg[p]);
+            v.push_back(o.xg[m]);
+            v.push_back(o.xc[r]);
+          }
+      break;
+    case 9:
+      for (int q = 0; q < o.Nfc; ++q) {
+        v.push_back(o.fa[q]);
+        v.push_back(o.fb[q]);
+        v.push_back(o.fc[q]);
+      }
+      break;
+    default: return fail(DGPYR_E_ARG, "unknown reference array");
+  }
+  *needed = (int64_t)v.size();
+  if (out) std::memcpy(out, v.data(), sizeof(double) * (size_t)std::min<int64_t>(len, *needed));
+  return DGPYR_OK;
+}
+
+dgpyr_status dgpyr_host_mesh(const dgpyr_mesh* mesh, int32_t N, int32_t* nbr,
+                             double* inv_length_max, int32_t* hex_groups) {
+  if (!mesh || !mesh->xyz || !mesh->e2v || mesh->nverts <= 0 || mesh->nelems <= 0)
+    return fail(DGPYR_E_ARG, "mesh arrays must be non-null with positive sizes");
+  if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
+  dgpyr::RefOps ops;
+  char msg[256];
+  if (!dgpyr::build_refops(N, ops, msg, sizeof msg)) return fail(DGPYR_E_STATE, msg);
+  dgpyr::MeshData md;
+  std::string err;
+  int rc = dgpyr::build_mesh(ops, mesh->nverts, mesh->xyz, mesh->nelems, mesh->e2v, mesh->rho,
+                             mesh->kappa, md, err);
+  if (rc != 0) return fail((dgpyr_status)rc, err);
+  if (nbr)
+    for (int64_t e = 0; e < md.K; ++e)
+      for (int f = 0; f < 5; ++f) nbr[5 * e + f] = md.conn[(size_t)e * 8 + f];
+  if (inv_length_max) *inv_length_max = md.inv_length_max;
+  if (hex_groups) *hex_groups = md.hex_groups ? 1 : 0;
+  return DGPYR_OK;
+}
+
+void dgpyr_destroy(dgpyr_ctx* c) {
+  if (!c) return;
+  hipDeviceSynchronize();
+  free_ctx(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Library context: reference operators and per-element data on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dgpyr.h"
+#include "host/mesh.hpp"
+#include "host/refops.hpp"
+
+namespace dgpyr {
+
+// Device copies of the reference operators (all FP64, row-major).
+struct DevOps {
+  const double* DrT;  // [Np][Nc]  d phi_n / dr at volume point q, transposed
+  const double* DsT;  // [Np][Nc]
+  const double* DtT;  // [Np][Nc]
+  const double* V;    // [Nc][Np]  phi_n at volume points
+  const double* VfT;  // [Np][Nfc] phi_n at face points, transposed
+  const double* Vf;   // [Nfc][Np]
+  const double* wv;   // [Nc]      reference volume weights
+  const double* wf;   // [Nfc]     face parameter weights
+  const double* fa;   // [Nfc]     collapsed a of face points
+  const double* fb;   // [Nfc]     collapsed b of face points
+  const double* xg;   // [N+1]     Gauss-Legendre nodes
+  const double* na;   // [Np]      (a, b) node of each basis function
+  const double* nb;   // [Np]
+  const double* wwc;  // [Np]      reference mass diagonal w_i^k w_j^k 2/(2k+3)
+  const int* perm;    // [10][Nfq] face-point permutations: quad o = 0..7, tri 8..9
+};
+
+// Per-element device arrays (see host/mesh.hpp for the layouts).
+struct DevMesh {
+  const double* verts;  // [K][16]
+  const int* conn;      // [K][8]
+  const double* mat;    // [K][4]
+  int64_t K;
+  int bc;
+  double alpha;
+};
+
+}  // namespace dgpyr
+
+struct dgpyr_ctx {
+  int N = 0, Np = 0, Nc = 0, Nfq = 0, Nfc = 0;
+  int64_t K = 0;
+  int precision = 0;
+  int bc = 0;
+  double alpha = 1.0;
+  double inv_length_max = 0.0;
+  bool hex_groups = false;
+  dgpyr::DevOps ops{};
+  dgpyr::DevMesh mesh{};
+  double* T = nullptr;    // [K][Nfc][4] face traces
+  double* vol = nullptr;  // [K][4][Np] volume contribution
+  int64_t device_bytes = 0;
+  std::vector<void*> allocs;
+};
+
+namespace dgpyr {
+
+// Kernel launchers (kernels_fp64.hip).  mode 0: out = dU/dt; mode 1: LSRK
+// stage R <- ra R + dt rhs (R not read when ra == 0), out(U) <- out + rb R.
+hipError_t launch_trace(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
+hipError_t launch_volume(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s);
+hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
+                          double* out, double* R, double ra, double rb, double dt, hipStream_t s);
+
+}  // namespace dgpyr

@@ -1,0 +1,214 @@
+// Per-element geometry checks and topological face matching.
+#include "mesh.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+
+#include "dgpyr.h"
+#include "../geom.hpp"
+
+namespace dgpyr {
+
+namespace {
+
+inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Vertices of each face in parametrisation order.
+//   quad (face 0): corner at (a,b) = (-1,-1), (1,-1), (1,1), (-1,1)
+//   triangles: edge start (sigma = -1), edge end (sigma = +1), apex
+const int kQuad[4] = {0, 1, 2, 3};
+const int kTri[4][3] = {{0, 3, 4}, {1, 2, 4}, {0, 1, 4}, {3, 2, 4}};
+
+struct FaceKey {
+  std::array<int64_t, 4> v;  // sorted vertex ids, triangles padded with -1
+  int64_t slot;              // 5 * elem + face
+  bool operator<(const FaceKey& o) const {
+    if (v != o.v) return v < o.v;
+    return slot < o.slot;
+  }
+};
+
+// Corner index of (a, b) in {-1, 1}^2 in the quad order above.
+inline int corner_of(int a, int b) {
+  if (b < 0) return a < 0 ? 0 : 1;
+  return a > 0 ? 2 : 3;
+}
+
+}  // namespace
+
+int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nelems,
+               const int64_t* e2v, const double* rho, const double* kappa, MeshData& md,
+               std::string& err) {
+  char buf[256];
+  const int64_t K = nelems;
+  md.K = K;
+  md.verts.assign((size_t)K * 16, 0.0);
+  md.conn.assign((size_t)K * 8, -1);
+  md.mat.assign((size_t)K * 4, 0.0);
+
+  for (int64_t e = 0; e < K; ++e)
+    for (int i = 0; i < 5; ++i) {
+      const int64_t v = e2v[5 * e + i];
+      if (v < 0 || v >= nverts) {
+        std::snprintf(buf, sizeof buf, "element %lld: vertex index %lld out of range",
+                      (long long)e, (long long)v);
+        err = buf;
+        return DGPYR_E_ARG;
+      }
+      for (int d = 0; d < 3; ++d) md.verts[(size_t)e * 16 + 3 * i + d] = xyz[3 * v + d];
+    }
+
+  // Geometry: J > 0 at the four base corners implies J > 0 everywhere, since J
+  // is bilinear in (a, b) and constant in c (Lemma 1).  Also |dK| / |K|.
+  const int n1 = ops.Nq1;
+  md.inv_length_max = 0.0;
+  for (int64_t e = 0; e < K; ++e) {
+    const double* x = &md.verts[(size_t)e * 16];
+    const double r = rho ? rho[e] : 1.0;
+    const double k = kappa ? kappa[e] : 1.0;
+    if (!(r > 0) || !(k > 0)) {
+      std::snprintf(buf, sizeof buf, "element %lld: rho and kappa must be positive", (long long)e);
+      err = buf;
+      return DGPYR_E_ARG;
+    }
+    md.mat[4 * e + 0] = k;
+    md.mat[4 * e + 1] = 1.0 / r;
+    md.mat[4 * e + 2] = std::sqrt(k / r) * r;
+    double adj[9], J;
+    for (int ca = -1; ca <= 1; ca += 2)
+      for (int cb = -1; cb <= 1; cb += 2) {
+        pyr_metric(x, ca, cb, adj, &J);
+        if (!(J > 0)) {
+          std::snprintf(buf, sizeof buf,
+                        "element %lld: Jacobian %.3e <= 0 at base corner (%d,%d); check the "
+                        "vertex order (base counter-clockwise seen from the apex)",
+                        (long long)e, J, ca, cb);
+          err = buf;
+          return DGPYR_E_MESH;
+        }
+      }
+    // volume = sum_q w_q J(a_q, b_q); J does not depend on c
+    double vol = 0.0;
+    for (int m = 0; m < n1; ++m)
+      for (int p = 0; p < n1; ++p) {
+        pyr_metric(x, ops.xg[p], ops.xg[m], adj, &J);
+        vol += ops.wg[p] * ops.wg[m] * J * (8.0 / 3.0) / 4.0;
+      }
+    // surface area |dK|: the base with the face rule (as the flux integrals
+    // are taken), the planar triangles in closed form
+    double area = 0.0;
+    for (int m = 0; m < n1; ++m)
+      for (int p = 0; p < n1; ++p) {
+        double nrm[3];
+        pyr_face_normal(x, 0, ops.xg[p], ops.xg[m], nrm);
+        area += ops.wg[p] * ops.wg[m] * std::sqrt(dot3(nrm, nrm));
+      }
+    for (int f = 1; f < 5; ++f) {
+      double nrm[3];
+      pyr_face_normal(x, f, 0.0, 0.0, nrm);
+      area += 2.0 * std::sqrt(dot3(nrm, nrm));  // parameter-space area of a triangle is 2
+    }
+    md.inv_length_max = std::max(md.inv_length_max, std::sqrt(k / r) * area / vol);
+  }
+
+  // Faces: sort by vertex set, pair equal keys.
+  std::vector<FaceKey> keys((size_t)K * 5);
+  for (int64_t e = 0; e < K; ++e) {
+    const int64_t* ev = &e2v[5 * e];
+    for (int f = 0; f < 5; ++f) {
+      FaceKey& fk = keys[(size_t)e * 5 + f];
+      fk.slot = 5 * e + f;
+      if (f == 0) {
+        for (int i = 0; i < 4; ++i) fk.v[i] = ev[kQuad[i]];
+      } else {
+        for (int i = 0; i < 3; ++i) fk.v[i] = ev[kTri[f - 1][i]];
+        fk.v[3] = -1;
+      }
+      std::sort(fk.v.begin(), fk.v.end());
+      for (int i = 1; i < 4; ++i)
+        if (fk.v[i] >= 0 && fk.v[i] == fk.v[i - 1]) {
+          std::snprintf(buf, sizeof buf, "element %lld face %d has a repeated vertex",
+                        (long long)e, f);
+          err = buf;
+          return DGPYR_E_MESH;
+        }
+    }
+  }
+  std::sort(keys.begin(), keys.end());
+  std::vector<uint32_t> code((size_t)K, 0u);
+  const size_t F = keys.size();
+  size_t i = 0;
+  while (i < F) {
+    size_t j = i + 1;
+    while (j < F && keys[j].v == keys[i].v) ++j;
+    if (j - i > 2) {
+      std::snprintf(buf, sizeof buf, "a face of element %lld is shared by %zu elements",
+                    (long long)(keys[i].slot / 5), j - i);
+      err = buf;
+      return DGPYR_E_NONCONFORMING;
+    }
+    if (j - i == 2) {
+      for (int side = 0; side < 2; ++side) {
+        const int64_t s0 = keys[i + side].slot, s1 = keys[i + 1 - side].slot;
+        const int64_t e0 = s0 / 5, e1 = s1 / 5;
+        const int f0 = (int)(s0 % 5), f1 = (int)(s1 % 5);
+        const int64_t* v0 = &e2v[5 * e0];
+        const int64_t* v1 = &e2v[5 * e1];
+        int orient = -1;
+        if (f0 == 0) {
+          if (f1 != 0) { orient = -1; }
+          else {
+            for (int o = 0; o < 8 && orient < 0; ++o) {
+              bool ok = true;
+              for (int ca = -1; ca <= 1 && ok; ca += 2)
+                for (int cb = -1; cb <= 1 && ok; cb += 2) {
+                  const bool swap = (o >> 2) & 1;
+                  int X = swap ? cb : ca, Y = swap ? ca : cb;
+                  if (o & 1) X = -X;
+                  if ((o >> 1) & 1) Y = -Y;
+                  ok = v0[kQuad[corner_of(ca, cb)]] == v1[kQuad[corner_of(X, Y)]];
+                }
+              if (ok) orient = o;
+            }
+          }
+        } else if (f1 != 0) {
+          const int* t0 = kTri[f0 - 1];
+          const int* t1 = kTri[f1 - 1];
+          if (v0[t0[2]] == v1[t1[2]]) {
+            if (v0[t0[0]] == v1[t1[0]] && v0[t0[1]] == v1[t1[1]]) orient = 0;
+            else if (v0[t0[0]] == v1[t1[1]] && v0[t0[1]] == v1[t1[0]]) orient = 1;
+          }
+        }
+        if (orient < 0) {
+          std::snprintf(buf, sizeof buf,
+                        "elements %lld and %lld share face vertices but their face "
+                        "parametrisations do not match (different face types or apexes)",
+                        (long long)e0, (long long)e1);
+          err = buf;
+          return DGPYR_E_NONCONFORMING;
+        }
+        md.conn[(size_t)e0 * 8 + f0] = (int32_t)e1;
+        code[e0] |= (uint32_t)(f1 | (orient << 3)) << (6 * f0);
+      }
+    }
+    i = j;
+  }
+  for (int64_t e = 0; e < K; ++e) md.conn[(size_t)e * 8 + 5] = (int32_t)code[e];
+
+  // Groups of 6 consecutive elements sharing an apex whose triangle faces all
+  // pair inside the group (pyramids from splitting a hexahedron).
+  md.hex_groups = (K % 6 == 0) && K > 0;
+  for (int64_t g = 0; md.hex_groups && g < K / 6; ++g)
+    for (int64_t e = 6 * g; e < 6 * g + 6 && md.hex_groups; ++e) {
+      if (e2v[5 * e + 4] != e2v[5 * 6 * g + 4]) md.hex_groups = false;
+      for (int f = 1; f < 5; ++f) {
+        const int32_t nb = md.conn[(size_t)e * 8 + f];
+        if (nb < 6 * g || nb >= 6 * g + 6) md.hex_groups = false;
+      }
+    }
+  return 0;
+}
+
+}  // namespace dgpyr

@@ -1,0 +1,33 @@
+// Host-side per-element geometry and face connectivity.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "refops.hpp"
+
+namespace dgpyr {
+
+// Per-element data handed to the device.
+//   verts  [K][16]: x0..x4 (15 doubles) and one pad.
+//   conn   [K][8] int32: neighbour element of faces 0..4 (-1 on the boundary),
+//          then one packed word: for face f, bits 6f..6f+2 hold the
+//          neighbour's face id and bits 6f+3..6f+5 the orientation code
+//          (quad: 0..7 as in quad_perm, triangle: 0..1 as in tri_perm).
+//   mat    [K][4]: kappa, 1/rho, rho*c, 0.
+struct MeshData {
+  int64_t K = 0;
+  std::vector<double> verts;
+  std::vector<int32_t> conn;
+  std::vector<double> mat;
+  double inv_length_max = 0.0;  // max_K c_K |dK| / |K|
+  bool hex_groups = false;
+};
+
+// Returns 0 on success or a negative dgpyr_status with a message in err.
+int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nelems,
+               const int64_t* e2v, const double* rho, const double* kappa, MeshData& md,
+               std::string& err);
+
+}  // namespace dgpyr

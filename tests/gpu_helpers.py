@@ -1,0 +1,29 @@
+"""Helpers shared by the GPU tests: run the library and compare with the oracle."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_rhs(solver, canon: np.ndarray) -> np.ndarray:
+    import torch
+    c = torch.from_numpy(np.ascontiguousarray(canon, dtype=np.float64)).cuda()
+    U = solver.pack(c)
+    out = solver.rhs(U)
+    res = solver.unpack(out)
+    torch.cuda.synchronize()
+    return res.cpu().numpy()
+
+
+def rel_err_per_field(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """max |got - ref| / max |ref| for each of the four fields."""
+    num = np.abs(got - ref).max(axis=(0, 2))
+    den = np.maximum(np.abs(ref).max(axis=(0, 2)), 1e-300)
+    return num / den

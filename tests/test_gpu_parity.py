@@ -1,0 +1,152 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: FP64 right-hand side within 1e-12 relative to the oracle, per field
+(max abs difference over all coefficients / max abs oracle value), in the
+canonical coefficient layout; LSRK trajectories within 1e-11.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_rhs, log, rel_err_per_field
+from oracle import AcousticDG, lsrk_run
+from oracle.dg import wall_mode
+from synth import hex_pyramid_mesh, octahedron_mesh, random_materials, random_state, single_pyramid
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _solver(xyz, e2v, N, **kw):
+    import paper_1502_07703_amd as dg
+    return dg.Solver(xyz, e2v, N, **kw)
+
+
+@pytest.mark.parametrize("N", list(range(0, 9)))
+def test_rhs_parity_cfg1_all_orders(N):
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    K = e2v.shape[0]
+    rho, kap = random_materials(K, seed=N)
+    U = random_state(K, N, seed=100 + N)
+    log(f"[parity] cfg1 N={N} K={K}")
+    ref = AcousticDG(xyz, e2v, N, rho=rho, kappa=kap).rhs(U)
+    with _solver(xyz, e2v, N, rho=rho, kappa=kap) as s:
+        got = gpu_rhs(s, U)
+    err = rel_err_per_field(got, ref)
+    log(f"[parity] cfg1 N={N} rel err per field {err}")
+    assert np.all(err < TOL), err
+
+
+@pytest.mark.parametrize("bc", ["wall", "free"])
+@pytest.mark.parametrize("alpha", [0.0, 1.0, 0.37])
+def test_rhs_parity_flux_and_bc(bc, alpha):
+    N = 3
+    xyz, e2v = hex_pyramid_mesh(2, seed=2)
+    K = e2v.shape[0]
+    rho, kap = random_materials(K, seed=5)
+    U = random_state(K, N, seed=7)
+    log(f"[parity] bc={bc} alpha={alpha}")
+    ref = AcousticDG(xyz, e2v, N, rho=rho, kappa=kap, bc=bc, alpha=alpha).rhs(U)
+    with _solver(xyz, e2v, N, rho=rho, kappa=kap, bc=bc, alpha=alpha) as s:
+        got = gpu_rhs(s, U)
+    assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_rhs_parity_shuffled_mesh(N):
+    """Element order permuted and base loops rotated: exercises every quad orientation."""
+    xyz, e2v = hex_pyramid_mesh(3, seed=3, shuffle=True)
+    K = e2v.shape[0]
+    U = random_state(K, N, seed=9)
+    log(f"[parity] shuffled K={K} N={N}")
+    ref = AcousticDG(xyz, e2v, N).rhs(U)
+    with _solver(xyz, e2v, N) as s:
+        got = gpu_rhs(s, U)
+    assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+@pytest.mark.parametrize("nsub", [1, 7, 13, 29])
+def test_rhs_parity_ragged_subsets(nsub):
+    """Meshes whose element counts leave partial workgroups (cut faces become walls)."""
+    N = 5
+    xyz, e2v = hex_pyramid_mesh(2, seed=4)
+    e2v = e2v[:nsub]
+    U = random_state(nsub, N, seed=nsub)
+    log(f"[parity] ragged K={nsub}")
+    ref = AcousticDG(xyz, e2v, N).rhs(U)
+    with _solver(xyz, e2v, N) as s:
+        got = gpu_rhs(s, U)
+    assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+def test_rhs_parity_special_meshes():
+    for (xyz, e2v) in (single_pyramid(), octahedron_mesh()):
+        for N in (0, 1, 3):
+            U = random_state(e2v.shape[0], N, seed=1)
+            ref = AcousticDG(xyz, e2v, N).rhs(U)
+            with _solver(xyz, e2v, N) as s:
+                got = gpu_rhs(s, U)
+            assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+def test_rhs_parity_eigenmode_data():
+    N = 3
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    o = AcousticDG(xyz, e2v, N)
+    U = o.project(wall_mode(1), xyz, e2v, t=0.2)
+    ref = o.rhs(U)
+    with _solver(xyz, e2v, N) as s:
+        got = gpu_rhs(s, U)
+    assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+def test_rhs_bitwise_deterministic():
+    import torch
+    N = 4
+    xyz, e2v = hex_pyramid_mesh(3, seed=6)
+    U = random_state(e2v.shape[0], N, seed=2)
+    with _solver(xyz, e2v, N) as s:
+        Ud = s.pack(torch.from_numpy(U).cuda())
+        a = s.rhs(Ud).clone()
+        b = s.rhs(Ud).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_step_parity_lsrk():
+    """A few LSRK(5,4) steps on the cfg1 mesh: GPU trajectory vs oracle trajectory."""
+    import torch
+    N = 3
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    o = AcousticDG(xyz, e2v, N)
+    U0 = o.project(wall_mode(1), xyz, e2v)
+    dt = 0.5 / (2.0 * (N + 1) * (N + 3) / 3.0 * o.inverse_length().max())
+    nsteps = 10
+    ref, _ = lsrk_run(o.rhs, U0, dt, nsteps)
+    with _solver(xyz, e2v, N) as s:
+        U = s.pack(torch.from_numpy(U0).cuda())
+        R = s.empty_state().fill_(float("nan"))  # R is never read before it is written
+        s.step(U, R, dt, nsteps)
+        got = s.unpack(U).cpu().numpy()
+    err = rel_err_per_field(got, ref)
+    log(f"[parity] LSRK 10 steps rel err {err}")
+    assert np.all(err < 1e-11), err
+
+
+@pytest.mark.parametrize("k1d,N,nsample", [(40, 4, 3000)])
+def test_rhs_parity_full_size_sampled(k1d, N, nsample):
+    """The benchmark workload (40^3 hexes x 6 = 384000 pyramids, N = 4): the GPU
+    computes every element; the oracle checks a seeded sample of elements."""
+    xyz, e2v = hex_pyramid_mesh(k1d, seed=2)
+    K = e2v.shape[0]
+    U = random_state(K, N, seed=11)
+    rng = np.random.default_rng(12)
+    sample = np.unique(np.concatenate([rng.choice(K, nsample, replace=False), [0, K - 1]]))
+    log(f"[parity] full-size K={K} N={N} sample={sample.size}")
+    with _solver(xyz, e2v, N) as s:
+        got = gpu_rhs(s, U)
+    ref = AcousticDG(xyz, e2v, N, elems=sample).rhs(U)
+    err = rel_err_per_field(got[sample], ref)
+    log(f"[parity] full-size rel err {err}")
+    assert np.all(err < TOL), err

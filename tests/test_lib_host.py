@@ -1,0 +1,165 @@
+"""CPU checks of libdgpyr.so: exported symbols, host builders against the oracle,
+and error paths that setup reports before it touches a device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import AcousticDG
+from oracle.basis import eval_basis_abc
+from oracle.rules import collapse, face_rules, volume_rule
+from synth import hex_pyramid_mesh, random_materials
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1502_07703_amd import _binding
+    _binding.lib()
+    return _binding
+
+
+def _host_ref(B, N, which):
+    L = B.lib()
+    need = ctypes.c_int64()
+    B.check(L.dgpyr_host_reference(N, which, None, 0, ctypes.byref(need)), "query")
+    out = np.empty(need.value)
+    B.check(L.dgpyr_host_reference(N, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   need.value, ctypes.byref(need)), "fetch")
+    return out
+
+
+def test_every_declared_symbol_is_exported(B):
+    hdr = open(os.path.join(ROOT, "include", "dgpyr.h")).read()
+    declared = set(re.findall(r"\b(dgpyr_[a-z_]+)\(", hdr))
+    assert declared, "no declarations parsed"
+    L = B.lib()
+    missing = [d for d in sorted(declared) if not hasattr(L, d)]
+    assert not missing, missing
+    assert declared == set(B.EXPORTS)
+
+
+def test_status_strings(B):
+    L = B.lib()
+    for s in range(-8, 1):
+        assert L.dgpyr_status_string(s)
+
+
+@pytest.mark.parametrize("N", [0, 1, 3, 5, 8])
+def test_host_volume_operators_match_oracle_basis(B, N):
+    Np = (N + 1) * (N + 2) * (2 * N + 3) // 6
+    pts = _host_ref(B, N, 8).reshape(-1, 3)
+    a, b, c = pts.T
+    V = _host_ref(B, N, 1).reshape(-1, Np)
+    Dr = _host_ref(B, N, 2).reshape(-1, Np)
+    Ds = _host_ref(B, N, 3).reshape(-1, Np)
+    Dt = _host_ref(B, N, 4).reshape(-1, Np)
+    from oracle.basis import eval_basis_rst
+    r, s, t = collapse(a, b, c)
+    V2, Dr2, Ds2, Dt2 = eval_basis_rst(N, r, s, t, deriv=True)
+    for X, Y in ((V, V2), (Dr, Dr2), (Ds, Ds2), (Dt, Dt2)):
+        assert np.abs(X - Y).max() <= 1e-12 * max(1.0, np.abs(Y).max())
+    # weights: same multiset of (point, weight) as the oracle's minimal rule
+    w = _host_ref(B, N, 0)
+    vr = volume_rule(N)
+    k1 = np.lexsort((c, b, a))
+    k2 = np.lexsort((vr["c"], vr["b"], vr["a"]))
+    assert np.allclose(np.stack([a, b, c, w])[:, k1],
+                       np.stack([vr["a"], vr["b"], vr["c"], vr["w"]])[:, k2], atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("N", [0, 2, 4, 7])
+def test_host_face_operators_match_oracle(B, N):
+    Np = (N + 1) * (N + 2) * (2 * N + 3) // 6
+    pts = _host_ref(B, N, 9).reshape(-1, 3)
+    Vf = _host_ref(B, N, 5).reshape(-1, Np)
+    V2, _, _, _ = eval_basis_abc(N, pts[:, 0], pts[:, 1], pts[:, 2])
+    assert np.abs(Vf - V2).max() <= 1e-12 * max(1.0, np.abs(V2).max())
+    wf = _host_ref(B, N, 6).reshape(5, -1)
+    # parameter-space areas: base 4, each triangle 2 (oracle's face rules agree)
+    fr = face_rules(N)
+    for f in range(5):
+        assert abs(wf[f].sum() - fr[f]["w"].sum()) < 1e-13
+    # reference mass diagonal = Lemma 3 on the reference pyramid
+    wwc = _host_ref(B, N, 7)
+    vr = volume_rule(N)
+    from oracle.basis import eval_basis_rst
+    Vo = eval_basis_rst(N, vr["r"], vr["s"], vr["t"])
+    assert np.allclose(wwc, np.einsum("q,qi,qi->i", vr["w"], Vo, Vo), atol=0, rtol=1e-12)
+
+
+def _host_mesh(B, xyz, e2v, N, rho=None, kappa=None):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    e2v = np.ascontiguousarray(e2v, dtype=np.int64)
+    dptr = ctypes.POINTER(ctypes.c_double)
+    m = B.Mesh(nverts=xyz.shape[0], xyz=xyz.ctypes.data_as(dptr), nelems=e2v.shape[0],
+               e2v=e2v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+               rho=None if rho is None else rho.ctypes.data_as(dptr),
+               kappa=None if kappa is None else kappa.ctypes.data_as(dptr), bc=0)
+    nbr = np.empty((e2v.shape[0], 5), dtype=np.int32)
+    il = ctypes.c_double()
+    hg = ctypes.c_int32()
+    st = B.lib().dgpyr_host_mesh(ctypes.byref(m), N, nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 ctypes.byref(il), ctypes.byref(hg))
+    return st, nbr, il.value, hg.value
+
+
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_host_connectivity_matches_oracle_geometric_matching(B, shuffle):
+    N = 2
+    xyz, e2v = hex_pyramid_mesh(3, seed=21, shuffle=shuffle)
+    rho, kap = random_materials(e2v.shape[0], seed=2)
+    st, nbr, il, hg = _host_mesh(B, xyz, e2v, N, rho, kap)
+    assert st == 0
+    o = AcousticDG(xyz, e2v, N, rho=rho, kappa=kap)
+    # oracle faces are t=-1, r=-1, r=-t, s=-1, s=-t = collapsed c=-1, a=-1, a=+1, b=-1, b=+1
+    assert np.array_equal(nbr, o.nb_elem.astype(np.int32))
+    c = np.sqrt(kap / rho)
+    assert abs(il - (c * o.inverse_length()).max()) < 1e-12 * il
+    assert hg == (0 if shuffle else 1)
+
+
+def test_setup_errors_before_device(B):
+    import paper_1502_07703_amd as dg
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, e2v, 9)
+    assert ex.value.status == B.E_ORDER
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, e2v[:, [0, 3, 2, 1, 4]], 2)  # base loop reversed -> J < 0
+    assert ex.value.status == B.E_MESH
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, np.concatenate([e2v, e2v[:1]]), 2)  # a face shared by 3 elements
+    assert ex.value.status == B.E_NONCONFORMING
+    bad = e2v.copy()
+    bad[0, 0] = xyz.shape[0] + 5
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, bad, 2)
+    assert ex.value.status == B.E_ARG
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, e2v, 2, rho=-np.ones(e2v.shape[0]))
+    assert ex.value.status == B.E_ARG
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, e2v, 2, precision="split_bf16", alpha=-1.0)
+    assert ex.value.status in (B.E_ARG, B.E_UNSUPPORTED)
+
+
+def test_nonconforming_triangle_apex(B):
+    """Two pyramids sharing three vertices where one side's apex is the other's base
+    corner: the collapsed face rules do not coincide, which setup must reject."""
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1],
+                    [-1, 0, 0.5], [-1, 1, 0.5], [-1, 0, 1.5]], dtype=np.float64)
+    # element 0: face a=-1 has vertices (v0, v3, v4) = (0, 3, 4) with apex 4.
+    # element 1 contains the triangle {0, 3, 4} with apex 0.
+    e0 = [0, 1, 2, 3, 4]
+    cand = [3, 6, 7, 4, 0]
+    x = xyz[cand]
+    tri = np.dot(np.cross(x[1] - x[0], x[3] - x[0]), x[4] - x[0])
+    if tri < 0:
+        cand = [cand[0], cand[3], cand[2], cand[1], cand[4]]
+    st, _, _, _ = _host_mesh(B, xyz, np.array([e0, cand]), 1)
+    assert st in (B.E_NONCONFORMING, B.E_MESH)
