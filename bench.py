@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--k1d", type=int, default=40)
     ap.add_argument("--N", type=int, default=4)
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--reference-kernels", action="store_true",
+                    help="plain FP64 vector-ALU kernels instead of the matrix-core ones")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -113,7 +115,8 @@ def main():
     xyz, e2v = hex_pyramid_mesh(args.k1d, seed=2)
     K = e2v.shape[0]
     Uh = random_state(K, N, seed=11, scale=1e-3)
-    solver = dg.Solver(xyz, e2v, N, precision=args.precision)
+    solver = dg.Solver(xyz, e2v, N, precision=args.precision,
+                       reference_kernels=args.reference_kernels)
     U = solver.pack(torch.from_numpy(Uh).cuda())
     R = solver.empty_state().zero_()
     dt = solver.stable_dt(0.5)
@@ -188,7 +191,8 @@ def main():
         "config": {"workload": f"unit cube, {args.k1d}^3 perturbed hexes x 6 = {K} pyramids, "
                                f"N={N}, 4 fields, walls, penalty flux, LSRK(5,4)",
                    "k1d": args.k1d, "nelems": K, "N": N, "Np": Np, "dof": 4 * Np * K,
-                   "precision": args.precision, "stages_per_step": 5, "dt": dt},
+                   "precision": args.precision, "stages_per_step": 5, "dt": dt,
+                   "kernels": "reference (vector ALU)" if args.reference_kernels else "matrix core"},
         "roofline": roof,
         "stage": whole,
         "kernels": kernels,

@@ -75,10 +75,14 @@ typedef struct {
   int32_t bc;           /* dgpyr_bc, applied on every face without a neighbour    */
 } dgpyr_mesh;
 
+/* dgpyr_opts.flags bits */
+#define DGPYR_FLAG_REFERENCE_KERNELS 1u /* plain FP64 vector-ALU kernels instead of the
+                                           matrix-core ones (same results to roundoff) */
+
 typedef struct {
   int32_t precision; /* dgpyr_precision                                           */
   double alpha;      /* penalty scale: 0 = central flux, 1 = the flux of 4.3      */
-  uint32_t flags;    /* reserved, must be 0                                       */
+  uint32_t flags;    /* DGPYR_FLAG_* bits; others must be 0                       */
 } dgpyr_opts;
 
 typedef struct {

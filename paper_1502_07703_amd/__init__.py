@@ -48,7 +48,7 @@ class Solver:
     """A mesh and a discretisation set up on the current HIP device."""
 
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
-                 precision="fp64", stream=None):
+                 precision="fp64", reference_kernels=False, stream=None):
         L = B.lib()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._e2v = np.ascontiguousarray(e2v, dtype=np.int64)
@@ -69,7 +69,8 @@ class Solver:
             rho=None if self._rho is None else self._rho.ctypes.data_as(dptr),
             kappa=None if self._kappa is None else self._kappa.ctypes.data_as(dptr),
             bc=B.BC[bc])
-        opts = B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=0)
+        flags = B.FLAG_REFERENCE_KERNELS if reference_kernels else 0
+        opts = B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=flags)
         handle = ctypes.c_void_p()
         st = L.dgpyr_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
                            _stream_handle(stream) if stream is not None else None,

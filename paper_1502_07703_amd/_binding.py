@@ -17,6 +17,7 @@ OK, E_ARG, E_ORDER, E_MESH, E_NONCONFORMING, E_HIP, E_OOM, E_STATE, E_UNSUPPORTE
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 BC = {"wall": 0, "free": 1}
 PRECISION = {"fp64": 0, "fp32_mfma": 1, "split_bf16": 2}
+FLAG_REFERENCE_KERNELS = 1
 
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (

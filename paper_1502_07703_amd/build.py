@@ -22,6 +22,7 @@ LIB = os.path.join(PKG, "libdgpyr.so")
 SOURCES = [
     "api.hip",
     "kernels_fp64.hip",
+    "kernels_mfma.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

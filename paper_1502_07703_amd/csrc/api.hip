@@ -125,17 +125,66 @@ const char* kKernelNames = "trace;volume;surface_update";
 hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, double* R, double ra,
                      double rb, double dt, hipStream_t s, LaunchTimer* tm) {
   if (tm) tm->begin(0);
-  hipError_t e = dgpyr::launch_trace(*c, U, c->T, s);
+  hipError_t e = c->reference_kernels ? dgpyr::launch_trace(*c, U, c->T, s)
+                                      : dgpyr::launch_trace_mfma(*c, U, c->T, s);
   if (tm) tm->end();
   if (e != hipSuccess) return e;
   if (tm) tm->begin(1);
-  e = dgpyr::launch_volume(*c, U, c->vol, s);
+  e = c->reference_kernels ? dgpyr::launch_volume(*c, U, c->vol, s)
+                           : dgpyr::launch_volume_mfma(*c, U, c->vol, s);
   if (tm) tm->end();
   if (e != hipSuccess) return e;
   if (tm) tm->begin(2);
-  e = dgpyr::launch_surface(*c, mode, c->T, c->vol, out, R, ra, rb, dt, s);
+  e = c->reference_kernels
+          ? dgpyr::launch_surface(*c, mode, c->T, c->vol, out, R, ra, rb, dt, s)
+          : dgpyr::launch_surface_mfma(*c, mode, c->T, c->vol, out, R, ra, rb, dt, s);
   if (tm) tm->end();
   return e;
+}
+
+// Operator fragments in MFMA B order (layouts in context.hpp).
+template <typename T>
+std::vector<T> frag_rows(const std::vector<double>& Op, int P, int Np) {
+  // B[k][j] = Op[16t + j][4c + k], tiles t over P points, chunks c over Np
+  const int NT = (P + 15) / 16, NCH = (Np + 3) / 4;
+  std::vector<T> out((size_t)NT * NCH * 64, (T)0);
+  for (int t = 0; t < NT; ++t)
+    for (int c = 0; c < NCH; ++c)
+      for (int l = 0; l < 64; ++l) {
+        const int q = 16 * t + l % 16, n = 4 * c + l / 16;
+        if (q < P && n < Np) out[((size_t)t * NCH + c) * 64 + l] = (T)Op[(size_t)q * Np + n];
+      }
+  return out;
+}
+
+template <typename T>
+std::vector<T> frag_proj(const std::vector<double>& Op, int P, int Np) {
+  // B[k][j] = Op[16t + 4c + k][16u + j], tiles t over P points, u over Np
+  const int NT = (P + 15) / 16, NIT = (Np + 15) / 16;
+  std::vector<T> out((size_t)NT * 4 * NIT * 64, (T)0);
+  for (int t = 0; t < NT; ++t)
+    for (int c = 0; c < 4; ++c)
+      for (int u = 0; u < NIT; ++u)
+        for (int l = 0; l < 64; ++l) {
+          const int q = 16 * t + 4 * c + l / 16, i = 16 * u + l % 16;
+          if (q < P && i < Np) out[(((size_t)t * 4 + c) * NIT + u) * 64 + l] = (T)Op[(size_t)q * Np + i];
+        }
+  return out;
+}
+
+template <typename T>
+dgpyr_status upload_frags(dgpyr_ctx* c, const dgpyr::RefOps& o) {
+  dgpyr_status st = DGPYR_OK;
+  const T* p = nullptr;
+  if (st == DGPYR_OK && (st = upload(c, frag_rows<T>(o.Dr, o.Nc, o.Np), &p, "DrF")) == DGPYR_OK) c->frag.DrF = p;
+  if (st == DGPYR_OK && (st = upload(c, frag_rows<T>(o.Ds, o.Nc, o.Np), &p, "DsF")) == DGPYR_OK) c->frag.DsF = p;
+  if (st == DGPYR_OK && (st = upload(c, frag_rows<T>(o.Dt, o.Nc, o.Np), &p, "DtF")) == DGPYR_OK) c->frag.DtF = p;
+  if (st == DGPYR_OK && (st = upload(c, frag_proj<T>(o.V, o.Nc, o.Np), &p, "VF")) == DGPYR_OK) c->frag.VF = p;
+  const double* pd = nullptr;
+  if (st == DGPYR_OK && (st = upload(c, frag_rows<double>(o.Vf, o.Nfc, o.Np), &pd, "VfF")) == DGPYR_OK)
+    c->frag.VfF = pd;
+  if (st == DGPYR_OK && (st = upload(c, frag_proj<T>(o.Vf, o.Nfc, o.Np), &p, "LfF")) == DGPYR_OK) c->frag.LfF = p;
+  return st;
 }
 
 void free_ctx(dgpyr_ctx* c) {
@@ -181,10 +230,14 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   if (mesh->nelems > (int64_t)0x7fffffff) return fail(DGPYR_E_ARG, "more than 2^31-1 elements");
   if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
   if (mesh->bc != DGPYR_BC_WALL && mesh->bc != DGPYR_BC_FREE) return fail(DGPYR_E_ARG, "bad bc");
-  if (opts->flags != 0) return fail(DGPYR_E_ARG, "flags must be 0");
+  if (opts->flags & ~(uint32_t)DGPYR_FLAG_REFERENCE_KERNELS)
+    return fail(DGPYR_E_ARG, "unknown flag bits");
   if (!(opts->alpha >= 0.0)) return fail(DGPYR_E_ARG, "alpha must be >= 0");
-  if (opts->precision != DGPYR_FP64)
-    return fail(DGPYR_E_UNSUPPORTED, "only the FP64 form is built in this library");
+  if (opts->precision != DGPYR_FP64 && opts->precision != DGPYR_FP32_MFMA)
+    return fail(opts->precision == DGPYR_SPLIT_BF16 ? DGPYR_E_UNSUPPORTED : DGPYR_E_ARG,
+                "precision form not built");
+  if ((opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) && opts->precision != DGPYR_FP64)
+    return fail(DGPYR_E_UNSUPPORTED, "the reference kernels are FP64 only");
 
   dgpyr_ctx* c = new (std::nothrow) dgpyr_ctx();
   if (!c) return fail(DGPYR_E_OOM, "host allocation failed");
@@ -213,6 +266,7 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   c->alpha = opts->alpha;
   c->inv_length_max = md.inv_length_max;
   c->hex_groups = md.hex_groups;
+  c->reference_kernels = (opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) != 0;
 
   std::vector<int> perm((size_t)10 * ops.Nfq);
   for (int o = 0; o < 8; ++o) dgpyr::quad_perm(N, o, &perm[(size_t)o * ops.Nfq]);
@@ -237,6 +291,8 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   UP(ops.wwc, wwc)
   UP(perm, perm)
 #undef UP
+  if (st == DGPYR_OK)
+    st = c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops) : upload_frags<double>(c, ops);
   if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
   if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
   if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");

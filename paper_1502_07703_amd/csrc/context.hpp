@@ -32,6 +32,23 @@ struct DevOps {
   const int* perm;    // [10][Nfq] face-point permutations: quad o = 0..7, tri 8..9
 };
 
+// Operators in MFMA B-fragment order (see mfma.hpp).  DrF, DsF, DtF, VF and
+// LfF are in the precision of the contraction form (double for FP64, float
+// for FP32_MFMA); the trace operator VfF is always double.
+//   DrF, DsF, DtF  [NTC][NCH][64]: D[16t + l%16][4c + l/16]       (derivatives)
+//   VF             [NTC][4][NIT][64]: V[16t + 4c + l/16][16u + l%16] (projection)
+//   VfF            [NTF][NCH][64]: Vf[16t + l%16][4c + l/16]      (trace)
+//   LfF            [NTF][4][NIT][64]: Vf[16t + 4c + l/16][16u + l%16] (lift)
+// Entries outside the operator are zero.
+struct FragOps {
+  const void* DrF;
+  const void* DsF;
+  const void* DtF;
+  const void* VF;
+  const void* VfF;
+  const void* LfF;
+};
+
 // Per-element device arrays (see host/mesh.hpp for the layouts).
 struct DevMesh {
   const double* verts;  // [K][16]
@@ -54,6 +71,8 @@ struct dgpyr_ctx {
   bool hex_groups = false;
   dgpyr::DevOps ops{};
   dgpyr::DevMesh mesh{};
+  dgpyr::FragOps frag{};
+  bool reference_kernels = false;  // plain FP64 VALU kernels instead of MFMA
   double* T = nullptr;    // [K][Nfc][4] face traces
   double* vol = nullptr;  // [K][4][Np] volume contribution
   int64_t device_bytes = 0;
@@ -68,5 +87,11 @@ hipError_t launch_trace(const dgpyr_ctx& c, const double* U, double* T, hipStrea
 hipError_t launch_volume(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s);
 hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
                           double* out, double* R, double ra, double rb, double dt, hipStream_t s);
+// Matrix-core kernels (kernels_mfma.hip).
+hipError_t launch_volume_mfma(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s);
+hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
+hipError_t launch_surface_mfma(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
+                               double* out, double* R, double ra, double rb, double dt,
+                               hipStream_t s);
 
 }  // namespace dgpyr

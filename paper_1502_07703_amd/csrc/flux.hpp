@@ -1,0 +1,79 @@
+// Penalty flux of the acoustic DG scheme at one face point (Section 4.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "context.hpp"
+#include "geom.hpp"
+
+namespace dgpyr {
+
+// Weighted flux at face point q (face f = q / Nfq) of element e, whose
+// vertices are x (15 doubles).  Reads the element's own trace and the
+// neighbour's trace from T ([K][Nfc][4]) through the connectivity code, or
+// builds the mirror state on a boundary face.  With [[a]] = a+ - a-, outward
+// unit normal n, tau_p = alpha / {rho c}, tau_u = alpha {rho c}:
+//   F[0]   = w sJ (n.[[u]] - tau_p [[p]]) / 2
+//   F[1+k] = w sJ n_k ([[p]] - tau_u n.[[u]]) / 2
+template <int Nfq>
+__device__ __forceinline__ void face_flux(const double* __restrict__ T, const DevOps& ops,
+                                          const DevMesh& mesh, const double* x, int64_t e, int q,
+                                          double F[4]) {
+  constexpr int Nfc = 5 * Nfq;
+  const int f = q / Nfq, qq = q - f * Nfq;
+  const double* tm = T + (e * Nfc + q) * 4;
+  const double pm = tm[0], um0 = tm[1], um1 = tm[2], um2 = tm[3];
+  double Nv[3];
+  pyr_face_normal(x, f, ops.fa[q], ops.fb[q], Nv);
+  const double sJ = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+  const double n0 = Nv[0] / sJ, n1 = Nv[1] / sJ, n2 = Nv[2] / sJ;
+  const double zm = mesh.mat[e * 4 + 2];
+  const int nb = mesh.conn[e * 8 + f];
+  double pp, up0, up1, up2, zp;
+  if (nb >= 0) {
+    const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+    const int nf = code & 7, o = code >> 3;
+    const int pi = ops.perm[(f == 0 ? o : 8 + o) * Nfq + qq];
+    const double* tp = T + ((int64_t)nb * Nfc + nf * Nfq + pi) * 4;
+    pp = tp[0]; up0 = tp[1]; up1 = tp[2]; up2 = tp[3];
+    zp = mesh.mat[(int64_t)nb * 4 + 2];
+  } else {
+    const double un = n0 * um0 + n1 * um1 + n2 * um2;
+    if (mesh.bc == DGPYR_BC_WALL) {
+      pp = pm; up0 = um0 - 2 * un * n0; up1 = um1 - 2 * un * n1; up2 = um2 - 2 * un * n2;
+    } else {
+      pp = -pm; up0 = um0; up1 = um1; up2 = um2;
+    }
+    zp = zm;
+  }
+  const double zavg = 0.5 * (zm + zp);
+  const double taup = mesh.alpha / zavg, tauu = mesh.alpha * zavg;
+  const double jp = pp - pm;
+  const double jun = n0 * (up0 - um0) + n1 * (up1 - um1) + n2 * (up2 - um2);
+  const double w = ops.wf[q] * sJ;
+  const double Pu = 0.5 * w * (jp - tauu * jun);
+  F[0] = 0.5 * w * (jun - taup * jp);
+  F[1] = n0 * Pu;
+  F[2] = n1 * Pu;
+  F[3] = n2 * Pu;
+}
+
+// Inverse mass, material scaling and output of one coefficient (Algorithm 3):
+// rhs_p = -kappa acc_p / M_ii, rhs_u = -(1/rho) acc_u / M_ii with the diagonal
+// M_ii = J(a_i, b_i) w_i w_j 2/(2k+3) of Lemma 3.  MODE 0 writes rhs; MODE 1
+// performs R <- ra R + dt rhs (R not read when ra == 0), U <- U + rb R.
+template <int MODE>
+__device__ __forceinline__ void finish_coeff(double acc, double minv, double mat, double* out,
+                                             double* R, int64_t idx, double ra, double rb,
+                                             double dt) {
+  const double rhs = -mat * minv * acc;
+  if (MODE == 0) {
+    out[idx] = rhs;
+  } else {
+    const double rn = (ra == 0.0 ? 0.0 : ra * R[idx]) + dt * rhs;
+    R[idx] = rn;
+    out[idx] += rb * rn;
+  }
+}
+
+}  // namespace dgpyr

@@ -1,0 +1,295 @@
+// Matrix-core kernels: the volume term (Algorithm 1) as two chained
+// contractions per wave with the pointwise metric between them, the trace
+// interpolation, and the surface lift + inverse mass + LSRK update
+// (Algorithms 2-3).  One wave owns 4 elements; a workgroup of 4 waves owns 16.
+#include <hip/hip_runtime.h>
+
+#include "context.hpp"
+#include "flux.hpp"
+#include "geom.hpp"
+#include "mfma.hpp"
+
+namespace dgpyr {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kEW = 4;                 // elements per wave
+constexpr int kEB = kWaves * kEW;      // elements per workgroup
+constexpr int kBlock = 64 * kWaves;
+
+// A operands of U for this wave: lane l holds U[e][f][4c + l/16] with (e, f)
+// the element and field of row l % 16 in the form's row order; zero beyond Np
+// or beyond the mesh.
+template <int N, int FORM>
+__device__ __forceinline__ void load_u_frags(const double* __restrict__ U, int64_t ew0, int64_t K,
+                                             int lane, typename Mma<FORM>::T* afr) {
+  using TT = Tiles<N>;
+  const int row = lane & 15, kq = lane >> 4;
+  const int64_t e = ew0 + Mma<FORM>::row_elem(row);
+  const int f = Mma<FORM>::row_field(row);
+  const double* src = U + (e * 4 + f) * TT::Np;
+#pragma unroll
+  for (int c = 0; c < TT::NCH; ++c) {
+    const int n = 4 * c + kq;
+    afr[c] = (e < K && n < TT::Np) ? (typename Mma<FORM>::T)src[n] : (typename Mma<FORM>::T)0;
+  }
+}
+
+// Volume term: Y_rho = D_rho U at 16 cubature points per tile (3 contractions),
+// then Q_p = w sum_rho,k adj[rho][k] d_rho u_k, Q_u_k = w sum_rho adj[rho][k] d_rho p
+// in FP64, then vol += V^T Q.  adj = J d(r,s,t)/dx is evaluated from the
+// element's vertices at the point's (a, b) (it is constant along c).
+template <int N, int FORM>
+__global__ __launch_bounds__(kBlock) void k_volume_mfma(const double* __restrict__ U,
+                                                        double* __restrict__ vol, FragOps fo,
+                                                        DevOps ops, DevMesh mesh) {
+  using TT = Tiles<N>;
+  using M = Mma<FORM>;
+  using T = typename M::T;
+  __shared__ double sX[kEB][16];
+  __shared__ T sQ[kWaves][16][17];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t eb0 = (int64_t)blockIdx.x * kEB;
+  for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
+    const int64_t e = eb0 + x / 16;
+    sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
+  }
+  const int64_t ew0 = eb0 + wv * kEW;
+  T afr[TT::NCH];
+  load_u_frags<N, FORM>(U, ew0, mesh.K, lane, afr);
+  __syncthreads();
+
+  const T* DrF = static_cast<const T*>(fo.DrF) + lane;
+  const T* DsF = static_cast<const T*>(fo.DsF) + lane;
+  const T* DtF = static_cast<const T*>(fo.DtF) + lane;
+  const T* VF = static_cast<const T*>(fo.VF) + lane;
+  const int de = lane >> 4, dq = lane & 15;
+  const int row = lane & 15, kq = lane >> 4;
+  const double* xv = sX[wv * kEW + de];
+  typename M::Acc z[TT::NIT];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) z[u] = M::zero();
+
+  for (int t = 0; t < TT::NTC; ++t) {
+    typename M::Acc yr = M::zero(), ys = M::zero(), yt = M::zero();
+    const size_t fb = (size_t)t * TT::NCH * 64;
+#pragma unroll
+    for (int c = 0; c < TT::NCH; ++c) {
+      yr = M::mma(afr[c], DrF[fb + c * 64], yr);
+      ys = M::mma(afr[c], DsF[fb + c * 64], ys);
+      yt = M::mma(afr[c], DtF[fb + c * 64], yt);
+    }
+    const int q = 16 * t + dq;
+    double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0, Q3 = 0.0;
+    if (q < TT::Nc) {
+      const int pm = q % TT::Nfq;
+      double adj[9], J;
+      pyr_metric(xv, ops.xg[pm % TT::n1], ops.xg[pm / TT::n1], adj, &J);
+      const double w = ops.wv[q];
+      const double d[3][4] = {{(double)yr[0], (double)yr[1], (double)yr[2], (double)yr[3]},
+                              {(double)ys[0], (double)ys[1], (double)ys[2], (double)ys[3]},
+                              {(double)yt[0], (double)yt[1], (double)yt[2], (double)yt[3]}};
+      double qp = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) qp += adj[3 * r + k] * d[r][1 + k];
+      Q0 = w * qp;
+      Q1 = w * (adj[0] * d[0][0] + adj[3] * d[1][0] + adj[6] * d[2][0]);
+      Q2 = w * (adj[1] * d[0][0] + adj[4] * d[1][0] + adj[7] * d[2][0]);
+      Q3 = w * (adj[2] * d[0][0] + adj[5] * d[1][0] + adj[8] * d[2][0]);
+    }
+    // D layout (element de, point dq, 4 fields) -> A layout (row (e, f), point k)
+    sQ[wv][M::row(de, 0)][dq] = (T)Q0;
+    sQ[wv][M::row(de, 1)][dq] = (T)Q1;
+    sQ[wv][M::row(de, 2)][dq] = (T)Q2;
+    sQ[wv][M::row(de, 3)][dq] = (T)Q3;
+    __syncthreads();
+    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const T a = sQ[wv][row][4 * c2 + kq];
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, VF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+    }
+    __syncthreads();
+  }
+  const int64_t e = ew0 + de;
+  if (e < mesh.K) {
+    double* o = vol + e * 4 * TT::Np;
+#pragma unroll
+    for (int u = 0; u < TT::NIT; ++u) {
+      const int i = 16 * u + dq;
+      if (i < TT::Np) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v * TT::Np + i] = (double)z[u][v];
+      }
+    }
+  }
+}
+
+// Trace interpolation U^f = V^f U at every face point (FP64 in every form:
+// jumps of traces are differences of O(1) values).  Lane l ends with all four
+// fields of element l/16 at face point 16t + l%16 and stores them as one
+// 32-byte vector into T[K][Nfc][4].
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_trace_mfma(const double* __restrict__ U,
+                                                       double* __restrict__ T, FragOps fo,
+                                                       int64_t K) {
+  using TT = Tiles<N>;
+  using M = Mma<0>;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t ew0 = (int64_t)blockIdx.x * kEB + wv * kEW;
+  double afr[TT::NCH];
+  load_u_frags<N, 0>(U, ew0, K, lane, afr);
+  const double* VfF = static_cast<const double*>(fo.VfF) + lane;
+  const int de = lane >> 4, dq = lane & 15;
+  const int64_t e = ew0 + de;
+  for (int t = 0; t < TT::NTF; ++t) {
+    M::Acc y = M::zero();
+    const size_t fb = (size_t)t * TT::NCH * 64;
+#pragma unroll
+    for (int c = 0; c < TT::NCH; ++c) y = M::mma(afr[c], VfF[fb + c * 64], y);
+    const int q = 16 * t + dq;
+    if (e < K && q < TT::Nfc) *reinterpret_cast<dx4*>(T + (e * TT::Nfc + q) * 4) = y;
+  }
+}
+
+// Surface term, inverse mass and LSRK update.  Per 16-point face tile each
+// lane evaluates the FP64 flux of one (element, face point); the fluxes are
+// transposed through LDS into A operands and lifted by L = V^f^T F on the
+// matrix cores; the epilogue adds the volume term and applies M^-1, the
+// material factors and the RK stage.
+template <int N, int FORM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restrict__ T,
+                                                         const double* __restrict__ vol,
+                                                         FragOps fo, DevOps ops, DevMesh mesh,
+                                                         double* out, double* R, double ra,
+                                                         double rb, double dt) {
+  using TT = Tiles<N>;
+  using M = Mma<FORM>;
+  using TV = typename M::T;
+  __shared__ double sX[kEB][16];
+  __shared__ TV sF[kWaves][16][17];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t eb0 = (int64_t)blockIdx.x * kEB;
+  for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
+    const int64_t e = eb0 + x / 16;
+    sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
+  }
+  __syncthreads();
+  const int64_t ew0 = eb0 + wv * kEW;
+  const int de = lane >> 4, dq = lane & 15;
+  const int row = lane & 15, kq = lane >> 4;
+  const int64_t e = ew0 + de;
+  const double* xv = sX[wv * kEW + de];
+  const TV* LfF = static_cast<const TV*>(fo.LfF) + lane;
+  typename M::Acc z[TT::NIT];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) z[u] = M::zero();
+  for (int t = 0; t < TT::NTF; ++t) {
+    const int q = 16 * t + dq;
+    double F[4] = {0.0, 0.0, 0.0, 0.0};
+    if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sF[wv][M::row(de, v)][dq] = (TV)F[v];
+    __syncthreads();
+    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const TV a = sF[wv][row][4 * c2 + kq];
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, LfF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+    }
+    __syncthreads();
+  }
+  if (e >= mesh.K) return;
+  const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+  const double* vo = vol + e * 4 * TT::Np;
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) {
+    const int i = 16 * u + dq;
+    if (i >= TT::Np) continue;
+    const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t idx = (e * 4 + v) * TT::Np + i;
+      finish_coeff<MODE>(vo[v * TT::Np + i] + (double)z[u][v], minv, v == 0 ? kap : irho, out, R,
+                         idx, ra, rb, dt);
+    }
+  }
+}
+
+template <int N>
+hipError_t trace_mfma_n(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
+  const int64_t nb = (c.K + kEB - 1) / kEB;
+  hipLaunchKernelGGL((k_trace_mfma<N>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T, c.frag, c.K);
+  return hipGetLastError();
+}
+
+template <int N, int FORM>
+hipError_t surface_mfma_n(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
+                          double* out, double* R, double ra, double rb, double dt, hipStream_t s) {
+  const int64_t nb = (c.K + kEB - 1) / kEB;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_surface_mfma<N, FORM, 0>), dim3((unsigned)nb), dim3(kBlock), 0, s, T, vol,
+                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+  else
+    hipLaunchKernelGGL((k_surface_mfma<N, FORM, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, T, vol,
+                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t surface_mfma_dispatch(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
+                                 double* out, double* R, double ra, double rb, double dt,
+                                 hipStream_t s) {
+  if (c.precision == DGPYR_FP32_MFMA) return surface_mfma_n<N, 1>(c, mode, T, vol, out, R, ra, rb, dt, s);
+  return surface_mfma_n<N, 0>(c, mode, T, vol, out, R, ra, rb, dt, s);
+}
+
+template <int N, int FORM>
+hipError_t volume_mfma_n(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s) {
+  const int64_t nb = (c.K + kEB - 1) / kEB;
+  hipLaunchKernelGGL((k_volume_mfma<N, FORM>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, vol,
+                     c.frag, c.ops, c.mesh);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t volume_mfma_dispatch(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s) {
+  if (c.precision == DGPYR_FP32_MFMA) return volume_mfma_n<N, 1>(c, U, vol, s);
+  return volume_mfma_n<N, 0>(c, U, vol, s);
+}
+
+}  // namespace
+
+#define DGPYR_DISPATCH_N(fn, ...)        \
+  switch (c.N) {                         \
+    case 0: return fn<0>(__VA_ARGS__);   \
+    case 1: return fn<1>(__VA_ARGS__);   \
+    case 2: return fn<2>(__VA_ARGS__);   \
+    case 3: return fn<3>(__VA_ARGS__);   \
+    case 4: return fn<4>(__VA_ARGS__);   \
+    case 5: return fn<5>(__VA_ARGS__);   \
+    case 6: return fn<6>(__VA_ARGS__);   \
+    case 7: return fn<7>(__VA_ARGS__);   \
+    case 8: return fn<8>(__VA_ARGS__);   \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_volume_mfma(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s) {
+  DGPYR_DISPATCH_N(volume_mfma_dispatch, c, U, vol, s)
+}
+
+hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
+  DGPYR_DISPATCH_N(trace_mfma_n, c, U, T, s)
+}
+
+hipError_t launch_surface_mfma(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
+                               double* out, double* R, double ra, double rb, double dt,
+                               hipStream_t s) {
+  DGPYR_DISPATCH_N(surface_mfma_dispatch, c, mode, T, vol, out, R, ra, rb, dt, s)
+}
+
+}  // namespace dgpyr

@@ -1,0 +1,73 @@
+// Matrix-core (MFMA) building blocks for gfx950.
+//
+// All contractions of the hot path have the shape Y[i][j] = sum_k A[i][k] B[k][j]
+// where the 16 rows i are (element, field) pairs of 4 elements x 4 fields,
+// k runs over basis functions or cubature points, and j over cubature points,
+// face points or basis functions.  With the 16x16x4 MFMA shapes, lane l of a
+// wave holds (measured on gfx950 with one-hot operands)
+//   A operand:  A[l % 16][l / 16]
+//   B operand:  B[l / 16][l % 16]
+//   D result, FP32 (v_mfma_f32_16x16x4f32):  D[4 (l / 16) + v][l % 16]
+//   D result, FP64 (v_mfma_f64_16x16x4f64):  D[4 v + l / 16][l % 16],  v = 0..3.
+// The row order of (element e, field f) is chosen per form so that in both
+// cases lane l ends owning all four fields (register v = field) of element
+// l / 16 at column l % 16 -- what the pointwise geometry and flux work needs:
+// FP32 rows are i = 4 e + f, FP64 rows are i = 4 f + e.
+// Operators are stored on the device in "fragment order": the 64 values of
+// one B operand are contiguous, so each operand load is one coalesced
+// 512-byte (FP64) or 256-byte (FP32) read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dgpyr {
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// Precision forms of the contractions.  FORM 0: FP64 operands, FP64
+// accumulation.  FORM 1: FP32 operands, FP32 accumulation.
+template <int FORM>
+struct Mma;
+
+template <>
+struct Mma<0> {
+  using T = double;
+  using Acc = dx4;
+  static __device__ __forceinline__ int row(int e, int f) { return 4 * f + e; }
+  static __device__ __forceinline__ int row_elem(int i) { return i & 3; }
+  static __device__ __forceinline__ int row_field(int i) { return i >> 2; }
+  static __device__ __forceinline__ Acc zero() { return Acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mma<1> {
+  using T = float;
+  using Acc = fx4;
+  static __device__ __forceinline__ int row(int e, int f) { return 4 * e + f; }
+  static __device__ __forceinline__ int row_elem(int i) { return i >> 2; }
+  static __device__ __forceinline__ int row_field(int i) { return i & 3; }
+  static __device__ __forceinline__ Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Tile counts for degree N.
+template <int N>
+struct Tiles {
+  static constexpr int n1 = N + 1;
+  static constexpr int Np = (N + 1) * (N + 2) * (2 * N + 3) / 6;
+  static constexpr int Nc = n1 * n1 * n1;
+  static constexpr int Nfq = n1 * n1;
+  static constexpr int Nfc = 5 * Nfq;
+  static constexpr int NCH = (Np + 3) / 4;     // k-chunks over basis functions
+  static constexpr int NTC = (Nc + 15) / 16;   // 16-column tiles of volume points
+  static constexpr int NTF = (Nfc + 15) / 16;  // 16-column tiles of face points
+  static constexpr int NIT = (Np + 15) / 16;   // 16-column tiles of basis functions
+};
+
+}  // namespace dgpyr

@@ -150,3 +150,32 @@ def test_rhs_parity_full_size_sampled(k1d, N, nsample):
     err = rel_err_per_field(got[sample], ref)
     log(f"[parity] full-size rel err {err}")
     assert np.all(err < TOL), err
+
+
+@pytest.mark.parametrize("N", [1, 4, 7])
+def test_rhs_parity_reference_kernels(N):
+    """The plain FP64 vector-ALU kernels (flag) meet the same bar as the default."""
+    xyz, e2v = hex_pyramid_mesh(2, seed=8)
+    K = e2v.shape[0]
+    rho, kap = random_materials(K, seed=9)
+    U = random_state(K, N, seed=10)
+    ref = AcousticDG(xyz, e2v, N, rho=rho, kappa=kap).rhs(U)
+    with _solver(xyz, e2v, N, rho=rho, kappa=kap, reference_kernels=True) as s:
+        got = gpu_rhs(s, U)
+    assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_rhs_fp32_mfma_form(N):
+    """FP32 matrix-core contractions (volume, lift) with FP64 geometry, traces,
+    flux, mass and state: error against the FP64 oracle at the FP32 level."""
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    K = e2v.shape[0]
+    U = random_state(K, N, seed=3)
+    ref = AcousticDG(xyz, e2v, N).rhs(U)
+    with _solver(xyz, e2v, N, precision="fp32_mfma") as s:
+        got = gpu_rhs(s, U)
+    err = rel_err_per_field(got, ref)
+    log(f"[fp32] N={N} rel err per field {err}")
+    assert np.all(err < 2e-5), err
+    assert np.any(err > 1e-10), "FP32 form gave FP64-accurate results: wrong kernels?"
