@@ -50,6 +50,9 @@ def kernel_work(name: str, N: int):
         return 32 * Nc * Np + 40 * Nc, 32 * Np + 32 * Np + 120
     if name == "surface_update":   # flux, LIFT, inverse mass, LSRK
         return 8 * Nfc * Np + 25 * Nfc + 24 * Np, 32 * Np * 5 + 32 * Nab + 152
+    if name == "stage":            # volume + surface + inverse mass + LSRK, fused
+        return (32 * Nc * Np + 40 * Nc + 8 * Nfc * Np + 25 * Nfc + 24 * Np,
+                32 * Np * 4 + 32 * Nab + 152)
     raise KeyError(name)
 
 
@@ -94,6 +97,10 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--reference-kernels", action="store_true",
                     help="plain FP64 vector-ALU kernels instead of the matrix-core ones")
+    ap.add_argument("--unfused", action="store_true",
+                    help="separate matrix-core volume and surface launches")
+    ap.add_argument("--sum-factorized", action="store_true",
+                    help="FP64 sum-factorised kernels")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -116,7 +123,8 @@ def main():
     K = e2v.shape[0]
     Uh = random_state(K, N, seed=11, scale=1e-3)
     solver = dg.Solver(xyz, e2v, N, precision=args.precision,
-                       reference_kernels=args.reference_kernels)
+                       reference_kernels=args.reference_kernels, unfused=args.unfused,
+                       sum_factorized=args.sum_factorized)
     U = solver.pack(torch.from_numpy(Uh).cuda())
     R = solver.empty_state().zero_()
     dt = solver.stable_dt(0.5)
@@ -192,7 +200,9 @@ def main():
                                f"N={N}, 4 fields, walls, penalty flux, LSRK(5,4)",
                    "k1d": args.k1d, "nelems": K, "N": N, "Np": Np, "dof": 4 * Np * K,
                    "precision": args.precision, "stages_per_step": 5, "dt": dt,
-                   "kernels": "reference (vector ALU)" if args.reference_kernels else "matrix core"},
+                   "kernels": ("reference (vector ALU)" if args.reference_kernels else
+                               "sum-factorised, fused" if args.sum_factorized else
+                               "matrix core, unfused" if args.unfused else "matrix core, fused")},
         "roofline": roof,
         "stage": whole,
         "kernels": kernels,

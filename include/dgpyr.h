@@ -78,6 +78,11 @@ typedef struct {
 /* dgpyr_opts.flags bits */
 #define DGPYR_FLAG_REFERENCE_KERNELS 1u /* plain FP64 vector-ALU kernels instead of the
                                            matrix-core ones (same results to roundoff) */
+#define DGPYR_FLAG_UNFUSED 2u           /* matrix-core volume and surface as separate
+                                           launches instead of one fused stage kernel */
+#define DGPYR_FLAG_SUM_FACTORIZED 4u    /* FP64 sum-factorised evaluation of the same
+                                           contractions through the collapsed tensor
+                                           structure of the basis (Section 4.4), fused */
 
 typedef struct {
   int32_t precision; /* dgpyr_precision                                           */
@@ -163,6 +168,23 @@ dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t
  * part. */
 dgpyr_status dgpyr_host_mesh(const dgpyr_mesh* mesh, int32_t N, int32_t* nbr,
                              double* inv_length_max, int32_t* hex_groups);
+
+/* Physical coordinates of the (N+1)^3 volume cubature points of every element
+ * (device [K][Nc][3], point order q = p + (N+1)(m + (N+1) r) for Gauss-Legendre
+ * a_p, b_m and Gauss-Jacobi(2,0) c_r, Section 4.1) and, if wJ is not NULL,
+ * the quadrature weights w_q J(a_q, b_q) (device [K][Nc]).  Asynchronous. */
+dgpyr_status dgpyr_volume_points(dgpyr_ctx* ctx, double* xyz, double* wJ, void* stream);
+
+/* L2 projection onto the semi-nodal basis by the minimal volume rule:
+ * U_i = sum_q w_q J_q phi_i(q) f_q / M_ii for each field, with M diagonal
+ * (Lemma 3).  f: device [K][4][Nc] values at the points of
+ * dgpyr_volume_points; U: device state array.  Asynchronous. */
+dgpyr_status dgpyr_project(dgpyr_ctx* ctx, const double* f, double* U, void* stream);
+
+/* Values of state U at the volume cubature points: f (device [K][4][Nc]).
+ * With the weights of dgpyr_volume_points this gives L2 norms and errors.
+ * Asynchronous. */
+dgpyr_status dgpyr_eval(dgpyr_ctx* ctx, const double* U, double* f, void* stream);
 
 /* Release every device buffer of the context (synchronises the device first).
  * NULL is accepted. */

@@ -48,7 +48,8 @@ class Solver:
     """A mesh and a discretisation set up on the current HIP device."""
 
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
-                 precision="fp64", reference_kernels=False, stream=None):
+                 precision="fp64", reference_kernels=False, unfused=False,
+                 sum_factorized=False, stream=None):
         L = B.lib()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._e2v = np.ascontiguousarray(e2v, dtype=np.int64)
@@ -69,7 +70,9 @@ class Solver:
             rho=None if self._rho is None else self._rho.ctypes.data_as(dptr),
             kappa=None if self._kappa is None else self._kappa.ctypes.data_as(dptr),
             bc=B.BC[bc])
-        flags = B.FLAG_REFERENCE_KERNELS if reference_kernels else 0
+        flags = (B.FLAG_REFERENCE_KERNELS if reference_kernels else 0) | \
+            (B.FLAG_UNFUSED if unfused else 0) | \
+            (B.FLAG_SUM_FACTORIZED if sum_factorized else 0)
         opts = B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=flags)
         handle = ctypes.c_void_p()
         st = L.dgpyr_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
@@ -118,6 +121,35 @@ class Solver:
                                    _dptr(R, self.state_len, "R"), float(t0), float(dt),
                                    int(nsteps), _stream_handle(stream)), "dgpyr_step")
         return U, R
+
+    # -- initial data and errors ------------------------------------------------------
+    def volume_points(self, stream=None):
+        """Physical cubature points (K, Nc, 3) and weights w J (K, Nc)."""
+        import torch
+        Nc = self.info["Nc"]
+        xyz = torch.empty((self.K, Nc, 3), dtype=torch.float64, device="cuda")
+        wJ = torch.empty((self.K, Nc), dtype=torch.float64, device="cuda")
+        B.check(B.lib().dgpyr_volume_points(self._h, _dptr(xyz), _dptr(wJ), _stream_handle(stream)),
+                "dgpyr_volume_points")
+        return xyz, wJ
+
+    def project(self, f, out=None, stream=None):
+        """L2 projection of values f (K, 4, Nc) at the cubature points -> state."""
+        out = self.empty_state() if out is None else out
+        B.check(B.lib().dgpyr_project(self._h, _dptr(f, self.K * 4 * self.info["Nc"], "f"),
+                                      _dptr(out, self.state_len, "U"), _stream_handle(stream)),
+                "dgpyr_project")
+        return out
+
+    def evaluate(self, U, out=None, stream=None):
+        """Values (K, 4, Nc) of state U at the cubature points."""
+        import torch
+        if out is None:
+            out = torch.empty((self.K, 4, self.info["Nc"]), dtype=torch.float64, device="cuda")
+        B.check(B.lib().dgpyr_eval(self._h, _dptr(U, self.state_len, "U"),
+                                   _dptr(out, self.K * 4 * self.info["Nc"], "f"),
+                                   _stream_handle(stream)), "dgpyr_eval")
+        return out
 
     def stable_dt(self, cfl=0.5):
         """CFL / (2(N+1)(N+3)/3 * max_K c_K |dK|/|K|) (Section 4.3 scaling)."""

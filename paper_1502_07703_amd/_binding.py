@@ -18,12 +18,15 @@ OK, E_ARG, E_ORDER, E_MESH, E_NONCONFORMING, E_HIP, E_OOM, E_STATE, E_UNSUPPORTE
 BC = {"wall": 0, "free": 1}
 PRECISION = {"fp64": 0, "fp32_mfma": 1, "split_bf16": 2}
 FLAG_REFERENCE_KERNELS = 1
+FLAG_UNFUSED = 2
+FLAG_SUM_FACTORIZED = 4
 
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
     "dgpyr_step", "dgpyr_step_timed", "dgpyr_kernel_names", "dgpyr_host_reference",
-    "dgpyr_host_mesh", "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
+    "dgpyr_host_mesh", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
+    "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
 )
 
 
@@ -92,6 +95,9 @@ def lib():
     L.dgpyr_host_mesh.argtypes = [POINTER(Mesh), c_int32, POINTER(c_int32), POINTER(c_double),
                                   POINTER(c_int32)]
     L.dgpyr_host_mesh.restype = c_int32
+    for name in ("dgpyr_volume_points", "dgpyr_project", "dgpyr_eval"):
+        getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        getattr(L, name).restype = c_int32
     L.dgpyr_destroy.argtypes = [c_void_p]
     L.dgpyr_destroy.restype = None
     L.dgpyr_status_string.argtypes = [c_int32]

@@ -23,6 +23,8 @@ SOURCES = [
     "api.hip",
     "kernels_fp64.hip",
     "kernels_mfma.hip",
+    "kernels_aux.hip",
+    "kernels_sf.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

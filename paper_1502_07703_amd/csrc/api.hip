@@ -119,16 +119,41 @@ struct LaunchTimer {
   }
 };
 
-const char* kKernelNames = "trace;volume;surface_update";
+// Kernel kinds per path, in dgpyr_step_timed order.
+const char* kNamesFused = "trace;stage";
+const char* kNamesSplit = "trace;volume;surface_update";
+
+const char* kernel_names(const dgpyr_ctx* c) {
+  return (c->reference_kernels || c->unfused) ? kNamesSplit : kNamesFused;
+}
 
 // One LSRK stage (mode 1) or one right-hand side evaluation (mode 0).
+// Default path: matrix-core trace, then the fused stage kernel.  Split paths
+// (reference vector-ALU kernels, or the unfused matrix-core kernels): trace,
+// volume, surface + update.
 hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, double* R, double ra,
                      double rb, double dt, hipStream_t s, LaunchTimer* tm) {
+  if (c->sum_factorized) {
+    if (tm) tm->begin(0);
+    hipError_t e = dgpyr::launch_trace_sf(*c, U, c->T, s);
+    if (tm) tm->end();
+    if (e != hipSuccess) return e;
+    if (tm) tm->begin(1);
+    e = dgpyr::launch_stage_sf(*c, mode, U, c->T, out, R, ra, rb, dt, s);
+    if (tm) tm->end();
+    return e;
+  }
   if (tm) tm->begin(0);
   hipError_t e = c->reference_kernels ? dgpyr::launch_trace(*c, U, c->T, s)
                                       : dgpyr::launch_trace_mfma(*c, U, c->T, s);
   if (tm) tm->end();
   if (e != hipSuccess) return e;
+  if (!c->reference_kernels && !c->unfused) {
+    if (tm) tm->begin(1);
+    e = dgpyr::launch_stage_mfma(*c, mode, U, c->T, out, R, ra, rb, dt, s);
+    if (tm) tm->end();
+    return e;
+  }
   if (tm) tm->begin(1);
   e = c->reference_kernels ? dgpyr::launch_volume(*c, U, c->vol, s)
                            : dgpyr::launch_volume_mfma(*c, U, c->vol, s);
@@ -230,8 +255,12 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   if (mesh->nelems > (int64_t)0x7fffffff) return fail(DGPYR_E_ARG, "more than 2^31-1 elements");
   if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
   if (mesh->bc != DGPYR_BC_WALL && mesh->bc != DGPYR_BC_FREE) return fail(DGPYR_E_ARG, "bad bc");
-  if (opts->flags & ~(uint32_t)DGPYR_FLAG_REFERENCE_KERNELS)
+  if (opts->flags & ~(uint32_t)(DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED |
+                                DGPYR_FLAG_SUM_FACTORIZED))
     return fail(DGPYR_E_ARG, "unknown flag bits");
+  if ((opts->flags & DGPYR_FLAG_SUM_FACTORIZED) &&
+      (opts->precision != DGPYR_FP64 || (opts->flags & (DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED))))
+    return fail(DGPYR_E_UNSUPPORTED, "the sum-factorised kernels are FP64 and fused only");
   if (!(opts->alpha >= 0.0)) return fail(DGPYR_E_ARG, "alpha must be >= 0");
   if (opts->precision != DGPYR_FP64 && opts->precision != DGPYR_FP32_MFMA)
     return fail(opts->precision == DGPYR_SPLIT_BF16 ? DGPYR_E_UNSUPPORTED : DGPYR_E_ARG,
@@ -267,6 +296,8 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   c->inv_length_max = md.inv_length_max;
   c->hex_groups = md.hex_groups;
   c->reference_kernels = (opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) != 0;
+  c->unfused = (opts->flags & DGPYR_FLAG_UNFUSED) != 0;
+  c->sum_factorized = (opts->flags & DGPYR_FLAG_SUM_FACTORIZED) != 0;
 
   std::vector<int> perm((size_t)10 * ops.Nfq);
   for (int o = 0; o < 8; ++o) dgpyr::quad_perm(N, o, &perm[(size_t)o * ops.Nfq]);
@@ -291,13 +322,24 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   UP(ops.wwc, wwc)
   UP(perm, perm)
 #undef UP
+  if (st == DGPYR_OK) st = upload(c, ops.xc, &c->xc, "xc");
+  if (st == DGPYR_OK) st = upload(c, ops.sfLa, &c->sf.La, "sfLa");
+  if (st == DGPYR_OK) st = upload(c, ops.sfDa, &c->sf.Da, "sfDa");
+  if (st == DGPYR_OK) st = upload(c, ops.sfLe, &c->sf.Le, "sfLe");
+  if (st == DGPYR_OK) st = upload(c, ops.sfG, &c->sf.G, "sfG");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGt, &c->sf.Gt, "sfGt");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGp, &c->sf.Gp, "sfGp");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGb, &c->sf.Gb, "sfGb");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGf, &c->sf.Gf, "sfGf");
+  if (st == DGPYR_OK) st = upload(c, ops.wc, &c->sf.wc, "sfwc");
   if (st == DGPYR_OK)
     st = c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops) : upload_frags<double>(c, ops);
   if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
   if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
   if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
   if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->T, "trace buffer");
-  if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->vol, "volume buffer");
+  if (st == DGPYR_OK && (c->reference_kernels || c->unfused))
+    st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->vol, "volume buffer");
   if (st != DGPYR_OK) {
     free_ctx(c);
     return st;
@@ -395,8 +437,8 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, dou
 }
 
 const char* dgpyr_kernel_names(const dgpyr_ctx* c) {
-  (void)c;
-  return kKernelNames;
+  if (!c) return "";
+  return kernel_names(c);
 }
 
 dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,
@@ -458,6 +500,27 @@ dgpyr_status dgpyr_host_mesh(const dgpyr_mesh* mesh, int32_t N, int32_t* nbr,
   if (inv_length_max) *inv_length_max = md.inv_length_max;
   if (hex_groups) *hex_groups = md.hex_groups ? 1 : 0;
   return DGPYR_OK;
+}
+
+dgpyr_status dgpyr_volume_points(dgpyr_ctx* c, double* xyz, double* wJ, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!xyz) return fail(DGPYR_E_ARG, "xyz is null");
+  hipError_t e = dgpyr::launch_points(*c, xyz, wJ, (hipStream_t)stream);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "volume points launch");
+}
+
+dgpyr_status dgpyr_project(dgpyr_ctx* c, const double* f, double* U, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!f || !U) return fail(DGPYR_E_ARG, "null array");
+  hipError_t e = dgpyr::launch_project(*c, f, U, (hipStream_t)stream);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "project launch");
+}
+
+dgpyr_status dgpyr_eval(dgpyr_ctx* c, const double* U, double* f, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!f || !U) return fail(DGPYR_E_ARG, "null array");
+  hipError_t e = dgpyr::launch_eval(*c, U, f, (hipStream_t)stream);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "eval launch");
 }
 
 void dgpyr_destroy(dgpyr_ctx* c) {

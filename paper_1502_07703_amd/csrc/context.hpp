@@ -49,6 +49,19 @@ struct FragOps {
   const void* LfF;
 };
 
+// One-dimensional factors for the sum-factorised kernels (host/refops.hpp).
+struct SfOps {
+  const double* La;  // [k][p][i]
+  const double* Da;  // [k][p][i]
+  const double* Le;  // [k][2][i]
+  const double* G;   // [r][k]
+  const double* Gt;  // [r][k]
+  const double* Gp;  // [r][k]
+  const double* Gb;  // [k]
+  const double* Gf;  // [m][k]
+  const double* wc;  // [N+1] Gauss-Jacobi(2,0) weights
+};
+
 // Per-element device arrays (see host/mesh.hpp for the layouts).
 struct DevMesh {
   const double* verts;  // [K][16]
@@ -73,6 +86,10 @@ struct dgpyr_ctx {
   dgpyr::DevMesh mesh{};
   dgpyr::FragOps frag{};
   bool reference_kernels = false;  // plain FP64 VALU kernels instead of MFMA
+  bool unfused = false;            // separate matrix-core volume and surface launches
+  bool sum_factorized = false;     // FP64 sum-factorised kernels
+  dgpyr::SfOps sf{};
+  const double* xc = nullptr;      // [N+1] Gauss-Jacobi(2,0) nodes in c
   double* T = nullptr;    // [K][Nfc][4] face traces
   double* vol = nullptr;  // [K][4][Np] volume contribution
   int64_t device_bytes = 0;
@@ -87,9 +104,21 @@ hipError_t launch_trace(const dgpyr_ctx& c, const double* U, double* T, hipStrea
 hipError_t launch_volume(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s);
 hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
                           double* out, double* R, double ra, double rb, double dt, hipStream_t s);
+// Initial data and evaluation (kernels_aux.hip).
+hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s);
+hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s);
+hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s);
 // Matrix-core kernels (kernels_mfma.hip).
 hipError_t launch_volume_mfma(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s);
 hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
+// Sum-factorised FP64 kernels (kernels_sf.hip).
+hipError_t launch_trace_sf(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
+hipError_t launch_stage_sf(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                           double* out, double* R, double ra, double rb, double dt, hipStream_t s);
+// Fused volume + surface + inverse mass (+ RK stage) in one launch.
+hipError_t launch_stage_mfma(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                             double* out, double* R, double ra, double rb, double dt,
+                             hipStream_t s);
 hipError_t launch_surface_mfma(const dgpyr_ctx& c, int mode, const double* T, const double* vol,
                                double* out, double* R, double ra, double rb, double dt,
                                hipStream_t s);

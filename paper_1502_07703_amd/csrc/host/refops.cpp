@@ -185,6 +185,39 @@ bool build_refops(int N, RefOps& o, char* msg, int msglen) {
         be.eval(a, b, c, &o.Vf[(size_t)q * Np], nullptr, nullptr, nullptr);
       }
 
+  // One-dimensional factors for the sum-factorised kernels.
+  o.sfLa.assign((size_t)n1 * n1 * n1, 0.0);
+  o.sfDa.assign((size_t)n1 * n1 * n1, 0.0);
+  o.sfLe.assign((size_t)n1 * 2 * n1, 0.0);
+  o.sfG.assign((size_t)n1 * n1, 0.0);
+  o.sfGt.assign((size_t)n1 * n1, 0.0);
+  o.sfGp.assign((size_t)n1 * n1, 0.0);
+  o.sfGb.assign((size_t)n1, 0.0);
+  o.sfGf.assign((size_t)n1 * n1, 0.0);
+  for (int k = 0; k <= N; ++k) {
+    const std::vector<double>& lev = be.lev[k];
+    for (int i = 0; i <= k; ++i) {
+      for (int p = 0; p < n1; ++p) {
+        o.sfLa[((size_t)k * n1 + p) * n1 + i] = k > 0 ? lagrange(lev, i, o.xg[p]) : 1.0;
+        o.sfDa[((size_t)k * n1 + p) * n1 + i] = k > 0 ? lagrange_d(lev, i, o.xg[p]) : 0.0;
+      }
+      o.sfLe[((size_t)k * 2 + 0) * n1 + i] = k > 0 ? lagrange(lev, i, -1.0) : 1.0;
+      o.sfLe[((size_t)k * 2 + 1) * n1 + i] = k > 0 ? lagrange(lev, i, 1.0) : 1.0;
+    }
+    const double alpha = 2.0 * k + 3.0;
+    for (int r = 0; r < n1; ++r) {
+      const double c = o.xc[r], h = 0.5 * (1.0 - c);
+      const double P = jacobi_p(N - k, alpha, 0.0, c), dP = jacobi_dp(N - k, alpha, 0.0, c);
+      const double hk = std::pow(h, k), hk1 = k > 0 ? std::pow(h, k - 1) : 0.0;
+      o.sfG[(size_t)r * n1 + k] = hk * P;
+      o.sfGt[(size_t)r * n1 + k] = hk1 * P;
+      o.sfGp[(size_t)r * n1 + k] = hk * dP - 0.5 * k * hk1 * P;
+      const double ct = o.xt[r], ht = 0.5 * (1.0 - ct);
+      o.sfGf[(size_t)r * n1 + k] = std::pow(ht, k) * jacobi_p(N - k, alpha, 0.0, ct);
+    }
+    o.sfGb[k] = jacobi_p(N - k, alpha, 0.0, -1.0);
+  }
+
   // Diagonal of the reference mass matrix (Lemma 3 with J = 1), by quadrature,
   // checked against w_i^k w_j^k 2/(2k+3) and against diagonality.
   o.wwc.assign(Np, 0.0);

@@ -46,6 +46,16 @@ struct RefOps {
   // function: M_nn(K) = J_K(na[n], nb[n]) * wwc[n].
   std::vector<double> wwc, na, nb;
   std::vector<int> bi, bj, bk;  // (i, j, k) of each basis index
+  // One-dimensional factors of the basis for sum factorisation, with
+  // n1 = N + 1 and h = (1 - c)/2, g_k = h^k P_{N-k}^{(2k+3,0)}:
+  std::vector<double> sfLa;  // [k][p][i] l^k_i(xg[p]), zero for i > k
+  std::vector<double> sfDa;  // [k][p][i] d/da l^k_i(xg[p])
+  std::vector<double> sfLe;  // [k][s][i] l^k_i(-1) (s = 0), l^k_i(+1) (s = 1)
+  std::vector<double> sfG;   // [r][k] g_k(xc[r])
+  std::vector<double> sfGt;  // [r][k] h^(k-1) P_{N-k}(xc[r]) (zero for k = 0)
+  std::vector<double> sfGp;  // [r][k] g_k'(xc[r])
+  std::vector<double> sfGb;  // [k]    g_k(-1)
+  std::vector<double> sfGf;  // [m][k] g_k(xt[m])
 };
 
 // Builds all reference data; returns false (with a message) if an internal

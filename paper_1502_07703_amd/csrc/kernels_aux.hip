@@ -1,0 +1,87 @@
+// Initial data and error evaluation on the volume cubature: physical points
+// and weights, L2 projection, and evaluation of a state at the points.
+// Not on the per-stage path; plain FP64 vector-ALU kernels.
+#include <hip/hip_runtime.h>
+
+#include "context.hpp"
+#include "geom.hpp"
+
+namespace dgpyr {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Physical coordinates x(a, b, c) = (1-c)/2 B(a, b) + (1+c)/2 x4 of every
+// volume cubature point and, optionally, the weight w_q J(a_q, b_q).
+__global__ void k_points(DevOps ops, DevMesh mesh, int n1, int Nc, const double* __restrict__ xc,
+                         double* __restrict__ xyz, double* __restrict__ wJ) {
+  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (gid >= mesh.K * Nc) return;
+  const int64_t e = gid / Nc;
+  const int q = (int)(gid - e * Nc);
+  const int p = q % n1, m = (q / n1) % n1, r = q / (n1 * n1);
+  const double a = ops.xg[p], b = ops.xg[m], c = xc[r];
+  const double* x = mesh.verts + e * 16;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double B = 0.25 * ((1 - a) * (1 - b) * x[d] + (1 + a) * (1 - b) * x[3 + d] +
+                             (1 + a) * (1 + b) * x[6 + d] + (1 - a) * (1 + b) * x[9 + d]);
+    xyz[gid * 3 + d] = 0.5 * (1 - c) * B + 0.5 * (1 + c) * x[12 + d];
+  }
+  if (wJ) wJ[gid] = ops.wv[q] * pyr_jac(x, a, b);
+}
+
+// U_i = sum_q w_q J_q phi_i(q) f_q / M_ii (M diagonal, Lemma 3), per field.
+__global__ void k_project(DevOps ops, DevMesh mesh, int Np, int Nc, int n1,
+                          const double* __restrict__ f, double* __restrict__ U) {
+  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (gid >= mesh.K * 4 * Np) return;
+  const int64_t e = gid / (4 * Np);
+  const int rem = (int)(gid - e * 4 * Np);
+  const int fld = rem / Np, i = rem - fld * Np;
+  const double* x = mesh.verts + e * 16;
+  const double* fe = f + (e * 4 + fld) * Nc;
+  double acc = 0.0;
+  for (int q = 0; q < Nc; ++q) {
+    const int p = q % n1, m = (q / n1) % n1;
+    acc += ops.wv[q] * pyr_jac(x, ops.xg[p], ops.xg[m]) * ops.V[(int64_t)q * Np + i] * fe[q];
+  }
+  U[gid] = acc / (pyr_jac(x, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+}
+
+// f_q = sum_n phi_n(q) U_n per field.
+__global__ void k_eval(DevOps ops, int64_t K, int Np, int Nc, const double* __restrict__ U,
+                       double* __restrict__ f) {
+  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (gid >= K * 4 * Nc) return;
+  const int64_t ef = gid / Nc;
+  const int q = (int)(gid - ef * Nc);
+  const double* u = U + ef * Np;
+  double acc = 0.0;
+  for (int n = 0; n < Np; ++n) acc += ops.V[(int64_t)q * Np + n] * u[n];
+  f[gid] = acc;
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s) {
+  hipLaunchKernelGGL(k_points, dim3(nblocks(c.K * c.Nc)), dim3(kThreads), 0, s, c.ops, c.mesh,
+                     c.N + 1, c.Nc, c.xc, xyz, wJ);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s) {
+  hipLaunchKernelGGL(k_project, dim3(nblocks(c.K * 4 * c.Np)), dim3(kThreads), 0, s, c.ops, c.mesh,
+                     c.Np, c.Nc, c.N + 1, f, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_eval, dim3(nblocks(c.K * 4 * c.Nc)), dim3(kThreads), 0, s, c.ops, c.K, c.Np,
+                     c.Nc, U, f);
+  return hipGetLastError();
+}
+
+}  // namespace dgpyr

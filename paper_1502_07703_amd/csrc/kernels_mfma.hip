@@ -220,6 +220,143 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
   }
 }
 
+// Fused stage: volume term and surface lift accumulate into the same
+// matrix-core accumulators, then inverse mass, material and the RK stage are
+// applied in the epilogue; the volume contribution never leaves registers.
+// In RK mode the kernel reads and writes only its own elements' U and R;
+// other workgroups read traces (T), never U, so in-place update is safe.
+template <int N, int FORM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stage_mfma(const double* __restrict__ U,
+                                                       const double* __restrict__ T, FragOps fo,
+                                                       DevOps ops, DevMesh mesh, double* out,
+                                                       double* R, double ra, double rb, double dt) {
+  using TT = Tiles<N>;
+  using M = Mma<FORM>;
+  using TV = typename M::T;
+  __shared__ double sX[kEB][16];
+  __shared__ TV sQ[kWaves][16][17];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t eb0 = (int64_t)blockIdx.x * kEB;
+  for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
+    const int64_t e = eb0 + x / 16;
+    sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
+  }
+  const int64_t ew0 = eb0 + wv * kEW;
+  TV afr[TT::NCH];
+  load_u_frags<N, FORM>(U, ew0, mesh.K, lane, afr);
+  __syncthreads();
+
+  const TV* DrF = static_cast<const TV*>(fo.DrF) + lane;
+  const TV* DsF = static_cast<const TV*>(fo.DsF) + lane;
+  const TV* DtF = static_cast<const TV*>(fo.DtF) + lane;
+  const TV* VF = static_cast<const TV*>(fo.VF) + lane;
+  const TV* LfF = static_cast<const TV*>(fo.LfF) + lane;
+  const int de = lane >> 4, dq = lane & 15;
+  const int row = lane & 15, kq = lane >> 4;
+  const int64_t e = ew0 + de;
+  const double* xv = sX[wv * kEW + de];
+  typename M::Acc z[TT::NIT];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) z[u] = M::zero();
+
+  // volume (Algorithm 1)
+  for (int t = 0; t < TT::NTC; ++t) {
+    typename M::Acc yr = M::zero(), ys = M::zero(), yt = M::zero();
+    const size_t fb = (size_t)t * TT::NCH * 64;
+#pragma unroll
+    for (int c = 0; c < TT::NCH; ++c) {
+      yr = M::mma(afr[c], DrF[fb + c * 64], yr);
+      ys = M::mma(afr[c], DsF[fb + c * 64], ys);
+      yt = M::mma(afr[c], DtF[fb + c * 64], yt);
+    }
+    const int q = 16 * t + dq;
+    double Q[4] = {0.0, 0.0, 0.0, 0.0};
+    if (q < TT::Nc) {
+      const int pm = q % TT::Nfq;
+      double adj[9], J;
+      pyr_metric(xv, ops.xg[pm % TT::n1], ops.xg[pm / TT::n1], adj, &J);
+      const double w = ops.wv[q];
+      double dr[4], ds[4], dtt[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        dr[v] = (double)yr[v];
+        ds[v] = (double)ys[v];
+        dtt[v] = (double)yt[v];
+      }
+      double qp = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) qp += adj[k] * dr[1 + k] + adj[3 + k] * ds[1 + k] + adj[6 + k] * dtt[1 + k];
+      Q[0] = w * qp;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Q[1 + k] = w * (adj[k] * dr[0] + adj[3 + k] * ds[0] + adj[6 + k] * dtt[0]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sQ[wv][M::row(de, v)][dq] = (TV)Q[v];
+    __syncthreads();
+    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const TV a = sQ[wv][row][4 * c2 + kq];
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, VF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+    }
+    __syncthreads();
+  }
+
+  // surface (Algorithm 2)
+  for (int t = 0; t < TT::NTF; ++t) {
+    const int q = 16 * t + dq;
+    double F[4] = {0.0, 0.0, 0.0, 0.0};
+    if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sQ[wv][M::row(de, v)][dq] = (TV)F[v];
+    __syncthreads();
+    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const TV a = sQ[wv][row][4 * c2 + kq];
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, LfF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+    }
+    __syncthreads();
+  }
+
+  // inverse mass, material, RK stage (Algorithm 3)
+  if (e >= mesh.K) return;
+  const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) {
+    const int i = 16 * u + dq;
+    if (i >= TT::Np) continue;
+    const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      finish_coeff<MODE>((double)z[u][v], minv, v == 0 ? kap : irho, out, R,
+                         (e * 4 + v) * TT::Np + i, ra, rb, dt);
+  }
+}
+
+template <int N, int FORM>
+hipError_t stage_mfma_n(const dgpyr_ctx& c, int mode, const double* U, const double* T, double* out,
+                        double* R, double ra, double rb, double dt, hipStream_t s) {
+  const int64_t nb = (c.K + kEB - 1) / kEB;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stage_mfma<N, FORM, 0>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T,
+                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+  else
+    hipLaunchKernelGGL((k_stage_mfma<N, FORM, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T,
+                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t stage_mfma_dispatch(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                               double* out, double* R, double ra, double rb, double dt,
+                               hipStream_t s) {
+  if (c.precision == DGPYR_FP32_MFMA) return stage_mfma_n<N, 1>(c, mode, U, T, out, R, ra, rb, dt, s);
+  return stage_mfma_n<N, 0>(c, mode, U, T, out, R, ra, rb, dt, s);
+}
+
 template <int N>
 hipError_t trace_mfma_n(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
   const int64_t nb = (c.K + kEB - 1) / kEB;
@@ -284,6 +421,12 @@ hipError_t launch_volume_mfma(const dgpyr_ctx& c, const double* U, double* vol, 
 
 hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
   DGPYR_DISPATCH_N(trace_mfma_n, c, U, T, s)
+}
+
+hipError_t launch_stage_mfma(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                             double* out, double* R, double ra, double rb, double dt,
+                             hipStream_t s) {
+  DGPYR_DISPATCH_N(stage_mfma_dispatch, c, mode, U, T, out, R, ra, rb, dt, s)
 }
 
 hipError_t launch_surface_mfma(const dgpyr_ctx& c, int mode, const double* T, const double* vol,

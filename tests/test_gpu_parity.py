@@ -23,15 +23,19 @@ def _solver(xyz, e2v, N, **kw):
     return dg.Solver(xyz, e2v, N, **kw)
 
 
+PATHS = {"mfma": {}, "sumfact": {"sum_factorized": True}}
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("N", list(range(0, 9)))
-def test_rhs_parity_cfg1_all_orders(N):
+def test_rhs_parity_cfg1_all_orders(N, path):
     xyz, e2v = hex_pyramid_mesh(2, seed=1)
     K = e2v.shape[0]
     rho, kap = random_materials(K, seed=N)
     U = random_state(K, N, seed=100 + N)
-    log(f"[parity] cfg1 N={N} K={K}")
+    log(f"[parity] cfg1 N={N} K={K} path={path}")
     ref = AcousticDG(xyz, e2v, N, rho=rho, kappa=kap).rhs(U)
-    with _solver(xyz, e2v, N, rho=rho, kappa=kap) as s:
+    with _solver(xyz, e2v, N, rho=rho, kappa=kap, **PATHS[path]) as s:
         got = gpu_rhs(s, U)
     err = rel_err_per_field(got, ref)
     log(f"[parity] cfg1 N={N} rel err per field {err}")
@@ -53,29 +57,31 @@ def test_rhs_parity_flux_and_bc(bc, alpha):
     assert np.all(rel_err_per_field(got, ref) < TOL)
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("N", [2, 4])
-def test_rhs_parity_shuffled_mesh(N):
+def test_rhs_parity_shuffled_mesh(N, path):
     """Element order permuted and base loops rotated: exercises every quad orientation."""
     xyz, e2v = hex_pyramid_mesh(3, seed=3, shuffle=True)
     K = e2v.shape[0]
     U = random_state(K, N, seed=9)
-    log(f"[parity] shuffled K={K} N={N}")
+    log(f"[parity] shuffled K={K} N={N} path={path}")
     ref = AcousticDG(xyz, e2v, N).rhs(U)
-    with _solver(xyz, e2v, N) as s:
+    with _solver(xyz, e2v, N, **PATHS[path]) as s:
         got = gpu_rhs(s, U)
     assert np.all(rel_err_per_field(got, ref) < TOL)
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("nsub", [1, 7, 13, 29])
-def test_rhs_parity_ragged_subsets(nsub):
+def test_rhs_parity_ragged_subsets(nsub, path):
     """Meshes whose element counts leave partial workgroups (cut faces become walls)."""
     N = 5
     xyz, e2v = hex_pyramid_mesh(2, seed=4)
     e2v = e2v[:nsub]
     U = random_state(nsub, N, seed=nsub)
-    log(f"[parity] ragged K={nsub}")
+    log(f"[parity] ragged K={nsub} path={path}")
     ref = AcousticDG(xyz, e2v, N).rhs(U)
-    with _solver(xyz, e2v, N) as s:
+    with _solver(xyz, e2v, N, **PATHS[path]) as s:
         got = gpu_rhs(s, U)
     assert np.all(rel_err_per_field(got, ref) < TOL)
 
@@ -114,7 +120,8 @@ def test_rhs_bitwise_deterministic():
         assert torch.equal(a, b)
 
 
-def test_step_parity_lsrk():
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_step_parity_lsrk(path):
     """A few LSRK(5,4) steps on the cfg1 mesh: GPU trajectory vs oracle trajectory."""
     import torch
     N = 3
@@ -124,7 +131,7 @@ def test_step_parity_lsrk():
     dt = 0.5 / (2.0 * (N + 1) * (N + 3) / 3.0 * o.inverse_length().max())
     nsteps = 10
     ref, _ = lsrk_run(o.rhs, U0, dt, nsteps)
-    with _solver(xyz, e2v, N) as s:
+    with _solver(xyz, e2v, N, **PATHS[path]) as s:
         U = s.pack(torch.from_numpy(U0).cuda())
         R = s.empty_state().fill_(float("nan"))  # R is never read before it is written
         s.step(U, R, dt, nsteps)
@@ -134,8 +141,9 @@ def test_step_parity_lsrk():
     assert np.all(err < 1e-11), err
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("k1d,N,nsample", [(40, 4, 3000)])
-def test_rhs_parity_full_size_sampled(k1d, N, nsample):
+def test_rhs_parity_full_size_sampled(k1d, N, nsample, path):
     """The benchmark workload (40^3 hexes x 6 = 384000 pyramids, N = 4): the GPU
     computes every element; the oracle checks a seeded sample of elements."""
     xyz, e2v = hex_pyramid_mesh(k1d, seed=2)
@@ -143,8 +151,8 @@ def test_rhs_parity_full_size_sampled(k1d, N, nsample):
     U = random_state(K, N, seed=11)
     rng = np.random.default_rng(12)
     sample = np.unique(np.concatenate([rng.choice(K, nsample, replace=False), [0, K - 1]]))
-    log(f"[parity] full-size K={K} N={N} sample={sample.size}")
-    with _solver(xyz, e2v, N) as s:
+    log(f"[parity] full-size K={K} N={N} sample={sample.size} path={path}")
+    with _solver(xyz, e2v, N, **PATHS[path]) as s:
         got = gpu_rhs(s, U)
     ref = AcousticDG(xyz, e2v, N, elems=sample).rhs(U)
     err = rel_err_per_field(got[sample], ref)
@@ -179,3 +187,15 @@ def test_rhs_fp32_mfma_form(N):
     log(f"[fp32] N={N} rel err per field {err}")
     assert np.all(err < 2e-5), err
     assert np.any(err > 1e-10), "FP32 form gave FP64-accurate results: wrong kernels?"
+
+
+@pytest.mark.parametrize("N", [2, 6])
+def test_rhs_parity_unfused_matrix_core(N):
+    """Separate matrix-core volume and surface launches (flag) meet the same bar."""
+    xyz, e2v = hex_pyramid_mesh(2, seed=12)
+    K = e2v.shape[0]
+    U = random_state(K, N, seed=13)
+    ref = AcousticDG(xyz, e2v, N).rhs(U)
+    with _solver(xyz, e2v, N, unfused=True) as s:
+        got = gpu_rhs(s, U)
+    assert np.all(rel_err_per_field(got, ref) < TOL)

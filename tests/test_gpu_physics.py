@@ -1,0 +1,140 @@
+"""GPU projection / evaluation parity, standing-wave runs, energy, and the
+precision form's error against the FP64 path (Section 4.3 experiments)."""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import log, rel_err_per_field
+from oracle import AcousticDG, lsrk_run
+from oracle.dg import wall_mode
+from synth import hex_pyramid_mesh
+
+pytestmark = pytest.mark.gpu
+
+
+def _mode_torch(m):
+    import torch
+    k = m * np.pi
+    om = np.sqrt(3.0) * k
+
+    def f(X, t):  # X (..., 3) -> (..., 4)
+        x, y, z = X[..., 0], X[..., 1], X[..., 2]
+        cx, cy, cz = torch.cos(k * x), torch.cos(k * y), torch.cos(k * z)
+        sx, sy, sz = torch.sin(k * x), torch.sin(k * y), torch.sin(k * z)
+        amp = np.sin(om * t) / np.sqrt(3.0)
+        return torch.stack([cx * cy * cz * np.cos(om * t), amp * sx * cy * cz,
+                            amp * cx * sy * cz, amp * cx * cy * sz], dim=-1)
+    return f
+
+
+def _project_mode(s, m, t=0.0):
+    xyz, wJ = s.volume_points()
+    f = _mode_torch(m)(xyz, t).permute(0, 2, 1).contiguous()
+    return s.project(f), xyz, wJ
+
+
+def _l2_error(s, U, m, t, xyz, wJ):
+    import torch
+    vals = s.evaluate(U)
+    f = _mode_torch(m)(xyz, t).permute(0, 2, 1)
+    return float(torch.sqrt((wJ[:, None, :] * (vals - f) ** 2).sum()).item())
+
+
+def _energy(s, U, xyz, wJ):
+    vals = s.evaluate(U)
+    return float(0.5 * (wJ[:, None, :] * vals ** 2).sum().item())
+
+
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_projection_matches_oracle_minimal_rule(N):
+    import paper_1502_07703_amd as dg
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    o = AcousticDG(xyz, e2v, N)
+    ref = o.project(wall_mode(1), xyz, e2v, t=0.3, extra=1)
+    with dg.Solver(xyz, e2v, N) as s:
+        U, _, _ = _project_mode(s, 1, 0.3)
+        got = s.unpack(U).cpu().numpy()
+    err = rel_err_per_field(got, ref)
+    log(f"[physics] projection N={N} rel err {err}")
+    assert np.all(err < 1e-12), err
+
+
+def test_points_weights_and_eval():
+    import torch
+
+    import paper_1502_07703_amd as dg
+    N = 3
+    xyz, e2v = hex_pyramid_mesh(3, seed=2)
+    with dg.Solver(xyz, e2v, N) as s:
+        P, wJ = s.volume_points()
+        assert abs(wJ.sum().item() - 1.0) < 1e-13          # unit cube volume
+        assert P.min().item() > 0.0 and P.max().item() < 1.0
+        # projecting values of a polynomial in the space reproduces it exactly
+        f = torch.stack([P[..., 0] * P[..., 1], P[..., 2], 1.0 + 0 * P[..., 0],
+                         P[..., 0] - 2 * P[..., 2]], dim=1).contiguous()
+        back = s.evaluate(s.project(f))
+        assert (back - f).abs().max().item() < 1e-12
+
+
+def test_standing_wave_trajectory_matches_oracle():
+    """LSRK run of the projected standing wave: GPU and oracle trajectories and
+    L2 errors (same minimal rule) agree."""
+    import paper_1502_07703_amd as dg
+    N, k1d, T = 2, 3, 0.05
+    xyz, e2v = hex_pyramid_mesh(k1d, seed=5)
+    o = AcousticDG(xyz, e2v, N)
+    U0 = o.project(wall_mode(1), xyz, e2v, extra=1)
+    dt0 = 0.5 / (2.0 * (N + 1) * (N + 3) / 3.0 * o.inverse_length().max())
+    n = int(np.ceil(T / dt0))
+    ref, _ = lsrk_run(o.rhs, U0, T / n, n)
+    e_ref = o.l2_error(ref, wall_mode(1), xyz, e2v, t=T, extra=1)
+    with dg.Solver(xyz, e2v, N) as s:
+        U, P, wJ = _project_mode(s, 1, 0.0)
+        R = s.empty_state()
+        s.step(U, R, T / n, n)
+        got = s.unpack(U).cpu().numpy()
+        e_gpu = _l2_error(s, U, 1, T, P, wJ)
+    assert np.all(rel_err_per_field(got, ref) < 1e-11)
+    log(f"[physics] L2 error oracle {e_ref:.6e} gpu {e_gpu:.6e}")
+    assert abs(e_gpu - e_ref) < 1e-9 * e_ref
+
+
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+def test_energy_on_gpu(alpha):
+    """Central flux: energy constant up to the RK error; penalty flux: decreasing."""
+    import paper_1502_07703_amd as dg
+    N = 3
+    xyz, e2v = hex_pyramid_mesh(3, seed=7)
+    with dg.Solver(xyz, e2v, N, alpha=alpha) as s:
+        U, P, wJ = _project_mode(s, 2, 0.1)
+        R = s.empty_state()
+        dt = s.stable_dt(0.5)
+        E = [_energy(s, U, P, wJ)]
+        for _ in range(5):
+            s.step(U, R, dt, 20)
+            E.append(_energy(s, U, P, wJ))
+    E = np.array(E)
+    log(f"[physics] alpha={alpha} energies {E}")
+    if alpha == 0.0:
+        assert np.abs(E / E[0] - 1.0).max() < 1e-6
+    else:
+        assert np.all(np.diff(E) < 0.0)
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_fp32_form_error_against_standing_wave(N):
+    """Both forms against the exact standing wave (mode m) after the same run."""
+    import paper_1502_07703_amd as dg
+    k1d, T, m = 4, 0.1, 2
+    xyz, e2v = hex_pyramid_mesh(k1d, seed=9)
+    errs = {}
+    for prec in ("fp64", "fp32_mfma"):
+        with dg.Solver(xyz, e2v, N, precision=prec) as s:
+            U, P, wJ = _project_mode(s, m, 0.0)
+            R = s.empty_state()
+            n = int(np.ceil(T / s.stable_dt(0.5)))
+            s.step(U, R, T / n, n)
+            errs[prec] = _l2_error(s, U, m, T, P, wJ)
+    log(f"[physics] N={N} L2 errors {errs}")
+    rel = abs(errs["fp32_mfma"] - errs["fp64"]) / errs["fp64"]
+    assert rel < 0.1, errs
