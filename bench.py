@@ -101,6 +101,9 @@ def main():
                     help="separate matrix-core volume and surface launches")
     ap.add_argument("--sum-factorized", action="store_true",
                     help="FP64 sum-factorised kernels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy a 256 MiB buffer 3 times (a plain copy "
+                         "of known size for scaling HBM counters)")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -194,7 +197,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "dtype": {"fp64": "f64", "fp32_mfma": "f32 contractions, f64 state",
+                  "split_bf16": "bf16x3 contractions, f64 state"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"unit cube, {args.k1d}^3 perturbed hexes x 6 = {K} pyramids, "
                                f"N={N}, 4 fields, walls, penalty flux, LSRK(5,4)",
@@ -207,6 +211,14 @@ def main():
         "stage": whole,
         "kernels": kernels,
     }
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xyz, e2v, N, Uh, args.cpu_sample)
     solver.close()

@@ -155,7 +155,12 @@ const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
  * (no device needed).  which: 0 volume weights [Nc]; 1 V [Nc][Np];
  * 2 d/dr [Nc][Np]; 3 d/ds; 4 d/dt; 5 face basis values [Nfc][Np]; 6 face
  * parameter weights [Nfc]; 7 reference mass diagonal [Np]; 8 volume points
- * (a, b, c) [Nc][3]; 9 face points (a, b, c) [Nfc][3].  Writes min(len,
+ * (a, b, c) [Nc][3]; 9 face points (a, b, c) [Nfc][3]; the one-dimensional
+ * factors of phi_ijk = l^k_i(a) l^k_j(b) g_k(c), n1 = N+1, h = (1-c)/2:
+ * 10 l^k_i(a_p) [k][p][i]; 11 d/da l^k_i(a_p); 12 l^k_i(-1), l^k_i(+1)
+ * [k][2][i]; 13 g_k(c_r) [r][k]; 14 h^(k-1) P_{N-k}(c_r) [r][k];
+ * 15 g_k'(c_r) [r][k]; 16 g_k(-1) [k]; 17 g_k at the Gauss-Jacobi(1,0) face
+ * nodes [m][k].  Writes min(len,
  * needed) doubles to out (out may be NULL to query) and the full size to
  * *needed.  Errors: E_ORDER, E_ARG. */
 dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,

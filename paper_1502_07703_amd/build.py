@@ -25,6 +25,7 @@ SOURCES = [
     "kernels_mfma.hip",
     "kernels_aux.hip",
     "kernels_sf.hip",
+    "kernels_bf16.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

@@ -150,7 +150,9 @@ hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, doubl
   if (e != hipSuccess) return e;
   if (!c->reference_kernels && !c->unfused) {
     if (tm) tm->begin(1);
-    e = dgpyr::launch_stage_mfma(*c, mode, U, c->T, out, R, ra, rb, dt, s);
+    e = c->precision == DGPYR_SPLIT_BF16
+            ? dgpyr::launch_stage_bf16(*c, mode, U, c->T, out, R, ra, rb, dt, s)
+            : dgpyr::launch_stage_mfma(*c, mode, U, c->T, out, R, ra, rb, dt, s);
     if (tm) tm->end();
     return e;
   }
@@ -212,6 +214,79 @@ dgpyr_status upload_frags(dgpyr_ctx* c, const dgpyr::RefOps& o) {
   return st;
 }
 
+// bf16 bit pattern of a float, round to nearest even (finite inputs).
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Split-BF16 fragments (layouts in context.hpp): hi = bf16(x), lo = bf16(x - hi).
+void frag_bf16_rows(const std::vector<double>& Op, int P, int Np, std::vector<uint16_t>& hi,
+                    std::vector<uint16_t>& lo) {
+  const int NT = (P + 15) / 16, NC = (Np + 31) / 32;
+  hi.assign((size_t)NT * NC * 64 * 8, 0);
+  lo.assign(hi.size(), 0);
+  for (int t = 0; t < NT; ++t)
+    for (int c = 0; c < NC; ++c)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j) {
+          const int q = 16 * t + l % 16, n = 32 * c + 8 * (l / 16) + j;
+          if (q >= P || n >= Np) continue;
+          const double x = Op[(size_t)q * Np + n];
+          const size_t idx = (((size_t)t * NC + c) * 64 + l) * 8 + j;
+          hi[idx] = bf16_bits((float)x);
+          lo[idx] = bf16_bits((float)(x - (double)bf16_value(hi[idx])));
+        }
+}
+
+void frag_bf16_proj(const std::vector<double>& Op, int P, int Np, std::vector<uint16_t>& hi,
+                    std::vector<uint16_t>& lo) {
+  const int NT = (P + 31) / 32, NIT = (Np + 15) / 16;
+  hi.assign((size_t)NT * NIT * 64 * 8, 0);
+  lo.assign(hi.size(), 0);
+  for (int t = 0; t < NT; ++t)
+    for (int u = 0; u < NIT; ++u)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j) {
+          const int q = 32 * t + 8 * (l / 16) + j, i = 16 * u + l % 16;
+          if (q >= P || i >= Np) continue;
+          const double x = Op[(size_t)q * Np + i];
+          const size_t idx = (((size_t)t * NIT + u) * 64 + l) * 8 + j;
+          hi[idx] = bf16_bits((float)x);
+          lo[idx] = bf16_bits((float)(x - (double)bf16_value(hi[idx])));
+        }
+}
+
+dgpyr_status upload_bf16(dgpyr_ctx* c, const dgpyr::RefOps& o) {
+  dgpyr_status st = DGPYR_OK;
+  std::vector<uint16_t> h, l;
+  const double* pd = nullptr;
+  if (st == DGPYR_OK && (st = upload(c, frag_rows<double>(o.Vf, o.Nfc, o.Np), &pd, "VfF")) == DGPYR_OK)
+    c->frag.VfF = pd;
+  struct Item { const std::vector<double>* op; int P; bool rows; const uint16_t** H; const uint16_t** L; };
+  const Item items[] = {{&o.Dr, o.Nc, true, &c->bf.DrH, &c->bf.DrL},
+                        {&o.Ds, o.Nc, true, &c->bf.DsH, &c->bf.DsL},
+                        {&o.Dt, o.Nc, true, &c->bf.DtH, &c->bf.DtL},
+                        {&o.V, o.Nc, false, &c->bf.VH, &c->bf.VL},
+                        {&o.Vf, o.Nfc, false, &c->bf.LfH, &c->bf.LfL}};
+  for (const Item& it : items) {
+    if (st != DGPYR_OK) break;
+    if (it.rows) frag_bf16_rows(*it.op, it.P, o.Np, h, l);
+    else frag_bf16_proj(*it.op, it.P, o.Np, h, l);
+    st = upload(c, h, it.H, "bf16 hi");
+    if (st == DGPYR_OK) st = upload(c, l, it.L, "bf16 lo");
+  }
+  return st;
+}
+
 void free_ctx(dgpyr_ctx* c) {
   if (!c) return;
   for (void* p : c->allocs) hipFree(p);
@@ -262,9 +337,11 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
       (opts->precision != DGPYR_FP64 || (opts->flags & (DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED))))
     return fail(DGPYR_E_UNSUPPORTED, "the sum-factorised kernels are FP64 and fused only");
   if (!(opts->alpha >= 0.0)) return fail(DGPYR_E_ARG, "alpha must be >= 0");
-  if (opts->precision != DGPYR_FP64 && opts->precision != DGPYR_FP32_MFMA)
-    return fail(opts->precision == DGPYR_SPLIT_BF16 ? DGPYR_E_UNSUPPORTED : DGPYR_E_ARG,
-                "precision form not built");
+  if (opts->precision != DGPYR_FP64 && opts->precision != DGPYR_FP32_MFMA &&
+      opts->precision != DGPYR_SPLIT_BF16)
+    return fail(DGPYR_E_ARG, "unknown precision form");
+  if (opts->precision == DGPYR_SPLIT_BF16 && (opts->flags & DGPYR_FLAG_UNFUSED))
+    return fail(DGPYR_E_UNSUPPORTED, "the split-BF16 form is fused only");
   if ((opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) && opts->precision != DGPYR_FP64)
     return fail(DGPYR_E_UNSUPPORTED, "the reference kernels are FP64 only");
 
@@ -333,7 +410,9 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   if (st == DGPYR_OK) st = upload(c, ops.sfGf, &c->sf.Gf, "sfGf");
   if (st == DGPYR_OK) st = upload(c, ops.wc, &c->sf.wc, "sfwc");
   if (st == DGPYR_OK)
-    st = c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops) : upload_frags<double>(c, ops);
+    st = c->precision == DGPYR_SPLIT_BF16 ? upload_bf16(c, ops)
+         : c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops)
+                                           : upload_frags<double>(c, ops);
   if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
   if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
   if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
@@ -474,6 +553,14 @@ dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t
         v.push_back(o.fc[q]);
       }
       break;
+    case 10: v = o.sfLa; break;
+    case 11: v = o.sfDa; break;
+    case 12: v = o.sfLe; break;
+    case 13: v = o.sfG; break;
+    case 14: v = o.sfGt; break;
+    case 15: v = o.sfGp; break;
+    case 16: v = o.sfGb; break;
+    case 17: v = o.sfGf; break;
     default: return fail(DGPYR_E_ARG, "unknown reference array");
   }
   *needed = (int64_t)v.size();

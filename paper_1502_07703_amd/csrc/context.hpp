@@ -49,6 +49,16 @@ struct FragOps {
   const void* LfF;
 };
 
+// Split-BF16 operator fragments (hi and lo parts, bf16 bit patterns), for
+// v_mfma_f32_16x16x32_bf16.  Derivative operators, chunk c of 32 basis
+// functions, tile t of 16 points:  [t][c][64][8]: D[16t + l%16][32c + 8(l/16) + j];
+// projection / lift, chunk t of 32 points, tile u of 16 basis functions:
+// [t][u][64][8]: V[32t + 8(l/16) + j][16u + l%16].  Zero outside the operator.
+struct Bf16Ops {
+  const uint16_t *DrH, *DrL, *DsH, *DsL, *DtH, *DtL;
+  const uint16_t *VH, *VL, *LfH, *LfL;
+};
+
 // One-dimensional factors for the sum-factorised kernels (host/refops.hpp).
 struct SfOps {
   const double* La;  // [k][p][i]
@@ -89,6 +99,7 @@ struct dgpyr_ctx {
   bool unfused = false;            // separate matrix-core volume and surface launches
   bool sum_factorized = false;     // FP64 sum-factorised kernels
   dgpyr::SfOps sf{};
+  dgpyr::Bf16Ops bf{};
   const double* xc = nullptr;      // [N+1] Gauss-Jacobi(2,0) nodes in c
   double* T = nullptr;    // [K][Nfc][4] face traces
   double* vol = nullptr;  // [K][4][Np] volume contribution
@@ -115,6 +126,10 @@ hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hip
 hipError_t launch_trace_sf(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
 hipError_t launch_stage_sf(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                            double* out, double* R, double ra, double rb, double dt, hipStream_t s);
+// Split-BF16 fused stage (kernels_bf16.hip).
+hipError_t launch_stage_bf16(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                             double* out, double* R, double ra, double rb, double dt,
+                             hipStream_t s);
 // Fused volume + surface + inverse mass (+ RK stage) in one launch.
 hipError_t launch_stage_mfma(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                              double* out, double* R, double ra, double rb, double dt,

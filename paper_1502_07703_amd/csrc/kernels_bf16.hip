@@ -1,0 +1,193 @@
+// Split-BF16 form of the fused stage: the volume derivative, volume projection
+// and lift contractions run as three bf16 matrix-core products per multiply
+// (hi*hi + hi*lo + lo*hi) with FP32 accumulation; traces, the pointwise
+// metric, the flux, the inverse mass and the RK state stay in FP64.
+// One wave owns 4 elements (rows i = 4 e + f); point tiles of 32 feed the
+// 32-deep contractions.
+#include <hip/hip_runtime.h>
+
+#include "context.hpp"
+#include "flux.hpp"
+#include "geom.hpp"
+#include "mfma.hpp"
+
+namespace dgpyr {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kEW = 4;
+constexpr int kEB = kWaves * kEW;
+constexpr int kBlock = 64 * kWaves;
+
+__device__ __forceinline__ bfx8 load_bf8(const uint16_t* p) {
+  return *reinterpret_cast<const bfx8*>(p);
+}
+
+// A operand pair from 8 FP64 values.
+__device__ __forceinline__ void split8(const double* x, bfx8& hi, bfx8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    __bf16 h, l;
+    split_bf16(x[j], h, l);
+    hi[j] = h;
+    lo[j] = l;
+  }
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict__ U,
+                                                       const double* __restrict__ T, Bf16Ops bo,
+                                                       DevOps ops, DevMesh mesh, double* out,
+                                                       double* R, double ra, double rb, double dt) {
+  using TT = Tiles<N>;
+  __shared__ double sX[kEB][16];
+  __shared__ double sQ[kWaves][16][33];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t eb0 = (int64_t)blockIdx.x * kEB;
+  for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
+    const int64_t e = eb0 + x / 16;
+    sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
+  }
+  const int64_t ew0 = eb0 + wv * kEW;
+  const int row = lane & 15, kq = lane >> 4;  // A: row, 8-wide k group
+  const int de = lane >> 4, dq = lane & 15;   // D: element, column
+  const int64_t e = ew0 + de;
+
+  // A operands of U (rows 4 e + f): lane holds U[e][f][32c + 8 kq + j]
+  bfx8 ah[TT::NCH32], al[TT::NCH32];
+  {
+    const int64_t ea = ew0 + (row >> 2);
+    const int f = row & 3;
+#pragma unroll
+    for (int c = 0; c < TT::NCH32; ++c) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = 32 * c + 8 * kq + j;
+        x[j] = (ea < mesh.K && n < TT::Np) ? U[(ea * 4 + f) * TT::Np + n] : 0.0;
+      }
+      split8(x, ah[c], al[c]);
+    }
+  }
+  __syncthreads();
+  const double* xv = sX[wv * kEW + de];
+  fx4 z[TT::NIT];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) z[u] = fx4{0.f, 0.f, 0.f, 0.f};
+
+  // volume (Algorithm 1): 32-point chunks of two 16-point derivative tiles
+  for (int t32 = 0; t32 < TT::NT32C; ++t32) {
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      const int t = 2 * t32 + sub;
+      fx4 yr = {0.f, 0.f, 0.f, 0.f}, ys = yr, yt = yr;
+      if (t < TT::NTC) {
+#pragma unroll
+        for (int c = 0; c < TT::NCH32; ++c) {
+          const size_t fo = (((size_t)t * TT::NCH32 + c) * 64 + lane) * 8;
+          yr = mma_bf16x3(ah[c], al[c], load_bf8(bo.DrH + fo), load_bf8(bo.DrL + fo), yr);
+          ys = mma_bf16x3(ah[c], al[c], load_bf8(bo.DsH + fo), load_bf8(bo.DsL + fo), ys);
+          yt = mma_bf16x3(ah[c], al[c], load_bf8(bo.DtH + fo), load_bf8(bo.DtL + fo), yt);
+        }
+      }
+      const int q = 16 * t + dq;
+      double Q[4] = {0.0, 0.0, 0.0, 0.0};
+      if (q < TT::Nc) {
+        const int pm = q % TT::Nfq;
+        double adj[9], J;
+        pyr_metric(xv, ops.xg[pm % TT::n1], ops.xg[pm / TT::n1], adj, &J);
+        const double w = ops.wv[q];
+        double qp = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          qp += adj[k] * (double)yr[1 + k] + adj[3 + k] * (double)ys[1 + k] +
+                adj[6 + k] * (double)yt[1 + k];
+        Q[0] = w * qp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          Q[1 + k] = w * (adj[k] * (double)yr[0] + adj[3 + k] * (double)ys[0] +
+                          adj[6 + k] * (double)yt[0]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sQ[wv][4 * de + v][16 * sub + dq] = Q[v];
+    }
+    __syncthreads();
+    bfx8 qh, ql;
+    split8(&sQ[wv][row][8 * kq], qh, ql);
+#pragma unroll
+    for (int u = 0; u < TT::NIT; ++u) {
+      const size_t fo = (((size_t)t32 * TT::NIT + u) * 64 + lane) * 8;
+      z[u] = mma_bf16x3(qh, ql, load_bf8(bo.VH + fo), load_bf8(bo.VL + fo), z[u]);
+    }
+    __syncthreads();
+  }
+
+  // surface (Algorithm 2): fluxes of 32 face points per chunk
+  for (int t32 = 0; t32 < TT::NT32F; ++t32) {
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      const int q = 32 * t32 + 16 * sub + dq;
+      double F[4] = {0.0, 0.0, 0.0, 0.0};
+      if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sQ[wv][4 * de + v][16 * sub + dq] = F[v];
+    }
+    __syncthreads();
+    bfx8 fh, fl;
+    split8(&sQ[wv][row][8 * kq], fh, fl);
+#pragma unroll
+    for (int u = 0; u < TT::NIT; ++u) {
+      const size_t fo = (((size_t)t32 * TT::NIT + u) * 64 + lane) * 8;
+      z[u] = mma_bf16x3(fh, fl, load_bf8(bo.LfH + fo), load_bf8(bo.LfL + fo), z[u]);
+    }
+    __syncthreads();
+  }
+
+  // inverse mass, material, RK stage (Algorithm 3)
+  if (e >= mesh.K) return;
+  const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) {
+    const int i = 16 * u + dq;
+    if (i >= TT::Np) continue;
+    const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      finish_coeff<MODE>((double)z[u][v], minv, v == 0 ? kap : irho, out, R,
+                         (e * 4 + v) * TT::Np + i, ra, rb, dt);
+  }
+}
+
+template <int N>
+hipError_t stage_bf16_n(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                        double* out, double* R, double ra, double rb, double dt, hipStream_t s) {
+  const int64_t nb = (c.K + kEB - 1) / kEB;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stage_bf16<N, 0>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T, c.bf,
+                       c.ops, c.mesh, out, R, ra, rb, dt);
+  else
+    hipLaunchKernelGGL((k_stage_bf16<N, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T, c.bf,
+                       c.ops, c.mesh, out, R, ra, rb, dt);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stage_bf16(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                             double* out, double* R, double ra, double rb, double dt,
+                             hipStream_t s) {
+  switch (c.N) {
+    case 0: return stage_bf16_n<0>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 1: return stage_bf16_n<1>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 2: return stage_bf16_n<2>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 3: return stage_bf16_n<3>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 4: return stage_bf16_n<4>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 5: return stage_bf16_n<5>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 6: return stage_bf16_n<6>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 7: return stage_bf16_n<7>(c, mode, U, T, out, R, ra, rb, dt, s);
+    case 8: return stage_bf16_n<8>(c, mode, U, T, out, R, ra, rb, dt, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dgpyr

@@ -56,6 +56,25 @@ struct Mma<1> {
   }
 };
 
+// Split-BF16 form: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); a product
+// is taken as hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation).  Lane l holds A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7, and the result D[4 (l / 16) + v][l % 16]
+// (measured on gfx950), so rows are i = 4 e + f as in the FP32 form.
+typedef __bf16 bfx8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)(float)x;
+  lo = (__bf16)(float)(x - (double)(float)hi);
+}
+
+__device__ __forceinline__ fx4 mma_bf16x3(bfx8 ah, bfx8 al, bfx8 bh, bfx8 bl, fx4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
 // Tile counts for degree N.
 template <int N>
 struct Tiles {
@@ -68,6 +87,9 @@ struct Tiles {
   static constexpr int NTC = (Nc + 15) / 16;   // 16-column tiles of volume points
   static constexpr int NTF = (Nfc + 15) / 16;  // 16-column tiles of face points
   static constexpr int NIT = (Np + 15) / 16;   // 16-column tiles of basis functions
+  static constexpr int NCH32 = (Np + 31) / 32;  // 32-deep k-chunks over basis functions
+  static constexpr int NT32C = (Nc + 31) / 32;  // 32-point chunks of volume points
+  static constexpr int NT32F = (Nfc + 31) / 32; // 32-point chunks of face points
 };
 
 }  // namespace dgpyr

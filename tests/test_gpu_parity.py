@@ -199,3 +199,21 @@ def test_rhs_parity_unfused_matrix_core(N):
     with _solver(xyz, e2v, N, unfused=True) as s:
         got = gpu_rhs(s, U)
     assert np.all(rel_err_per_field(got, ref) < TOL)
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_rhs_split_bf16_form(N):
+    """Split-BF16 matrix-core contractions (three bf16 products per multiply, FP32
+    accumulation) with FP64 geometry, traces, flux, mass and state.  Each split
+    operand keeps about 16 mantissa bits, so the right-hand side is accurate to
+    roughly 1e-5 relative."""
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    K = e2v.shape[0]
+    U = random_state(K, N, seed=4)
+    ref = AcousticDG(xyz, e2v, N).rhs(U)
+    with _solver(xyz, e2v, N, precision="split_bf16") as s:
+        got = gpu_rhs(s, U)
+    err = rel_err_per_field(got, ref)
+    log(f"[bf16] N={N} rel err per field {err}")
+    assert np.all(err < 2e-4), err
+    assert np.any(err > 1e-10), "split-BF16 form gave FP64-accurate results: wrong kernels?"

@@ -128,7 +128,7 @@ def test_fp32_form_error_against_standing_wave(N):
     k1d, T, m = 4, 0.1, 2
     xyz, e2v = hex_pyramid_mesh(k1d, seed=9)
     errs = {}
-    for prec in ("fp64", "fp32_mfma"):
+    for prec in ("fp64", "fp32_mfma", "split_bf16"):
         with dg.Solver(xyz, e2v, N, precision=prec) as s:
             U, P, wJ = _project_mode(s, m, 0.0)
             R = s.empty_state()
@@ -136,5 +136,6 @@ def test_fp32_form_error_against_standing_wave(N):
             s.step(U, R, T / n, n)
             errs[prec] = _l2_error(s, U, m, T, P, wJ)
     log(f"[physics] N={N} L2 errors {errs}")
-    rel = abs(errs["fp32_mfma"] - errs["fp64"]) / errs["fp64"]
-    assert rel < 0.1, errs
+    for prec in ("fp32_mfma", "split_bf16"):
+        rel = abs(errs[prec] - errs["fp64"]) / errs["fp64"]
+        assert rel < 0.1, errs

@@ -163,3 +163,48 @@ def test_nonconforming_triangle_apex(B):
         cand = [cand[0], cand[3], cand[2], cand[1], cand[4]]
     st, _, _, _ = _host_mesh(B, xyz, np.array([e0, cand]), 1)
     assert st in (B.E_NONCONFORMING, B.E_MESH)
+
+
+@pytest.mark.parametrize("N", [1, 3, 4, 6])
+def test_sum_factorisation_tables_rebuild_dense_operators(B, N):
+    """The one-dimensional factors used by the sum-factorised kernels rebuild V,
+    Dr, Ds, Dt and the face values exactly (phi_ijk = l_i(a) l_j(b) g_k(c))."""
+    n1 = N + 1
+    Np = (N + 1) * (N + 2) * (2 * N + 3) // 6
+    La = _host_ref(B, N, 10).reshape(n1, n1, n1)   # [k][p][i]
+    Da = _host_ref(B, N, 11).reshape(n1, n1, n1)
+    Le = _host_ref(B, N, 12).reshape(n1, 2, n1)    # [k][s][i]
+    G = _host_ref(B, N, 13).reshape(n1, n1)        # [r][k]
+    Gt = _host_ref(B, N, 14).reshape(n1, n1)
+    Gp = _host_ref(B, N, 15).reshape(n1, n1)
+    Gb = _host_ref(B, N, 16)
+    Gf = _host_ref(B, N, 17).reshape(n1, n1)       # [m][k]
+    V = _host_ref(B, N, 1).reshape(-1, Np)
+    Dr = _host_ref(B, N, 2).reshape(-1, Np)
+    Ds = _host_ref(B, N, 3).reshape(-1, Np)
+    Dt = _host_ref(B, N, 4).reshape(-1, Np)
+    Vf = _host_ref(B, N, 5).reshape(5, n1, n1, Np)  # [f][m][p][n]
+    pts = _host_ref(B, N, 8).reshape(n1, n1, n1, 3)  # [r][m][p]
+    ijk = [(i, j, k) for k in range(n1) for j in range(k + 1) for i in range(k + 1)]
+    V2 = np.zeros((n1, n1, n1, Np)); Dr2 = np.zeros_like(V2); Ds2 = np.zeros_like(V2); Dt2 = np.zeros_like(V2)
+    F2 = np.zeros((5, n1, n1, Np))
+    for n, (i, j, k) in enumerate(ijk):
+        for r in range(n1):
+            for m in range(n1):
+                for p in range(n1):
+                    a, b = pts[r, m, p, 0], pts[r, m, p, 1]
+                    V2[r, m, p, n] = La[k, p, i] * La[k, m, j] * G[r, k]
+                    Dr2[r, m, p, n] = Da[k, p, i] * La[k, m, j] * Gt[r, k]
+                    Ds2[r, m, p, n] = La[k, p, i] * Da[k, m, j] * Gt[r, k]
+                    Dt2[r, m, p, n] = (La[k, p, i] * La[k, m, j] * Gp[r, k]
+                                       + 0.5 * (1 + a) * Dr2[r, m, p, n] + 0.5 * (1 + b) * Ds2[r, m, p, n])
+        for m in range(n1):
+            for p in range(n1):
+                F2[0, m, p, n] = La[k, p, i] * La[k, m, j] * Gb[k]
+                F2[1, m, p, n] = Le[k, 0, i] * La[k, p, j] * Gf[m, k]
+                F2[2, m, p, n] = Le[k, 1, i] * La[k, p, j] * Gf[m, k]
+                F2[3, m, p, n] = La[k, p, i] * Le[k, 0, j] * Gf[m, k]
+                F2[4, m, p, n] = La[k, p, i] * Le[k, 1, j] * Gf[m, k]
+    for X, Y in ((V, V2), (Dr, Dr2), (Ds, Ds2), (Dt, Dt2)):
+        assert np.abs(X - Y.reshape(-1, Np)).max() <= 1e-12 * max(1.0, np.abs(X).max())
+    assert np.abs(Vf - F2).max() <= 1e-12 * max(1.0, np.abs(Vf).max())
