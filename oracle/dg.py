@@ -64,6 +64,42 @@ def _face_geometry(verts, N, npts=None):
     return xs, ns, ws, rules
 
 
+def ricker(t, f0, t0=None):
+    """Ricker wavelet (1 - 2 pi^2 f0^2 tau^2) exp(-pi^2 f0^2 tau^2), tau = t - t0,
+    t0 = 1/f0 by default."""
+    t0 = 1.0 / f0 if t0 is None else t0
+    a = (np.pi * f0 * (t - t0)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def locate_point(verts, x, tol=1e-12, maxit=50):
+    """Reference coordinates (r, s, t) of physical point x in a pyramid with
+    vertices verts (5, 3), by Newton iteration on Bedrosian's vertex map from
+    the reference centroid.  Returns (rst, inside) with inside judged on the
+    reference pyramid r, s in [-1, -t], t in [-1, 1] (slack 1e-10)."""
+    lo, hi = verts.min(axis=0), verts.max(axis=0)
+    pad = 1e-9 * max(1.0, float(np.abs(hi - lo).max()))
+    if np.any(x < lo - pad) or np.any(x > hi + pad):
+        return None, False
+    rst = np.array([-0.5, -0.5, -0.5])
+    for _ in range(maxit):
+        r, s, t = rst
+        t = min(t, 1.0 - 1e-12)
+        X = map_points(verts[None], np.array([r]), np.array([s]), np.array([t]))[0, 0]
+        G = jacobian_matrix(verts[None], np.array([r]), np.array([s]), np.array([t]))[0, 0]
+        try:
+            d = np.linalg.solve(G, x - X)
+        except np.linalg.LinAlgError:
+            return None, False
+        rst = np.array([r, s, t]) + d
+        if np.linalg.norm(d) < tol:
+            break
+    r, s, t = rst
+    sl = 1e-10
+    inside = (-1 - sl <= t <= 1 + sl) and (-1 - sl <= r <= -t + sl) and (-1 - sl <= s <= -t + sl)
+    return rst, inside
+
+
 class AcousticDG:
     """Acoustic DG right-hand side on a pyramid mesh.
 
@@ -73,7 +109,7 @@ class AcousticDG:
     """
 
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
-                 elems=None, match_tol=1e-9, vol_npts=None, face_npts=None):
+                 elems=None, match_tol=1e-9, vol_npts=None, face_npts=None, sources=None):
         xyz = np.asarray(xyz, dtype=np.float64)
         e2v = np.asarray(e2v, dtype=np.int64)
         K = e2v.shape[0]
@@ -164,6 +200,25 @@ class AcousticDG:
             self.nb_perm.append(perm)
         self.nb_elem = nb_elem
 
+        # ---- point sources: f = amp R(t) delta(x - x_s) in the pressure equation
+        # (Section 4.3 right-hand side b); b_i = amp R(t) phi_i(xi_s) in the
+        # element containing x_s (lowest element index among those containing it)
+        self.sources = []
+        for src in (sources or []):
+            xs = np.asarray(src["x"], dtype=np.float64)
+            found = None
+            for row, e in enumerate(S):
+                rst, inside = locate_point(xyz[e2v[e]], xs)
+                if inside:
+                    found = (row, rst)
+                    break
+            if found is None:
+                continue  # not inside the evaluated subset
+            row, rst = found
+            phi = eval_basis_rst(N, rst[:1], rst[1:2], rst[2:3])[0]
+            self.sources.append(dict(row=row, phi=phi, f0=float(src["f0"]),
+                                     t0=src.get("t0"), amp=float(src.get("amp", 1.0)), rst=rst))
+
     # ------------------------------------------------------------------------
     def _material(self, idx):
         rho, kap = self.rho[idx], self.kappa[idx]
@@ -241,6 +296,9 @@ class AcousticDG:
                 surf[:, 1 + d] += np.einsum("qi,eq->ei", self.Vf[f], wf * n[:, :, d] * Pu)
 
         tot = vol + surf
+        for src in self.sources:
+            # dp/dt = -kappa M^-1 (vol + surf - b)
+            tot[src["row"], 0] -= src["amp"] * ricker(t, src["f0"], src["t0"]) * src["phi"]
         out = np.einsum("eij,efj->efi", self.Minv, tot)
         out[:, 0] *= -kapS[:, None]
         out[:, 1:] *= -(1.0 / rhoS)[:, None, None]

@@ -76,10 +76,19 @@ struct SfOps {
 struct DevMesh {
   const double* verts;  // [K][16]
   const int* conn;      // [K][8]
-  const double* mat;    // [K][4]
+  const double* mat;    // [K][4]: kappa, 1/rho, rho c, time-step scale
   int64_t K;
   int bc;
   double alpha;
+  // Point sources (Section 4.3 right-hand side b): src_of[e] is the source
+  // index of element e or -1; src_phi [nsrc][Np] = phi_i(xi_s);
+  // src_par [nsrc][4] = amplitude, f0, delay, 0.  The stage time of element e
+  // is t_base + t_tau * mat[e][3].
+  const int* src_of;
+  const double* src_phi;
+  const double* src_par;
+  double t_base;
+  double t_tau;
 };
 
 }  // namespace dgpyr

@@ -58,6 +58,25 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ T, const De
   F[3] = n2 * Pu;
 }
 
+// Ricker wavelet (1 - 2 a) exp(-a), a = (pi f0 (t - delay))^2.
+__device__ __forceinline__ double ricker_wavelet(double t, double f0, double delay) {
+  const double x = 3.14159265358979323846 * f0 * (t - delay);
+  const double a = x * x;
+  return (1.0 - 2.0 * a) * exp(-a);
+}
+
+// Point-source contribution b_i = amp R(t) phi_i(xi_s) to the pressure
+// coefficient i of element e (zero for elements without a source).
+template <int Np>
+__device__ __forceinline__ double source_term(const DevMesh& mesh, int64_t e, int i) {
+  if (!mesh.src_of) return 0.0;
+  const int s = mesh.src_of[e];
+  if (s < 0) return 0.0;
+  const double* par = mesh.src_par + 4 * s;
+  const double t = mesh.t_base + mesh.t_tau * mesh.mat[e * 4 + 3];
+  return par[0] * ricker_wavelet(t, par[1], par[2]) * mesh.src_phi[(int64_t)s * Np + i];
+}
+
 // Inverse mass, material scaling and output of one coefficient (Algorithm 3):
 // rhs_p = -kappa acc_p / M_ii, rhs_u = -(1/rho) acc_u / M_ii with the diagonal
 // M_ii = J(a_i, b_i) w_i w_j 2/(2k+3) of Lemma 3.  MODE 0 writes rhs; MODE 1

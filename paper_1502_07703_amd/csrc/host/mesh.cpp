@@ -76,6 +76,7 @@ int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nel
     md.mat[4 * e + 0] = k;
     md.mat[4 * e + 1] = 1.0 / r;
     md.mat[4 * e + 2] = std::sqrt(k / r) * r;
+    md.mat[4 * e + 3] = 1.0;  // time-step scale (per-problem dt in batches)
     double adj[9], J;
     for (int ca = -1; ca <= 1; ca += 2)
       for (int cb = -1; cb <= 1; cb += 2) {

@@ -15,7 +15,7 @@ namespace dgpyr {
 //          then one packed word: for face f, bits 6f..6f+2 hold the
 //          neighbour's face id and bits 6f+3..6f+5 the orientation code
 //          (quad: 0..7 as in quad_perm, triangle: 0..1 as in tri_perm).
-//   mat    [K][4]: kappa, 1/rho, rho*c, 0.
+//   mat    [K][4]: kappa, 1/rho, rho*c, time-step scale (1 for one problem).
 struct MeshData {
   int64_t K = 0;
   std::vector<double> verts;

@@ -146,15 +146,18 @@ __global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict_
   // inverse mass, material, RK stage (Algorithm 3)
   if (e >= mesh.K) return;
   const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+  const double dte = dt * mesh.mat[e * 4 + 3];
 #pragma unroll
   for (int u = 0; u < TT::NIT; ++u) {
     const int i = 16 * u + dq;
     if (i >= TT::Np) continue;
     const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      finish_coeff<MODE>((double)z[u][v], minv, v == 0 ? kap : irho, out, R,
-                         (e * 4 + v) * TT::Np + i, ra, rb, dt);
+    for (int v = 0; v < 4; ++v) {
+      const double acc = (double)z[u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);
+      finish_coeff<MODE>(acc, minv, v == 0 ? kap : irho, out, R, (e * 4 + v) * TT::Np + i, ra,
+                         rb, dte);
+    }
   }
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "context.hpp"
+#include "flux.hpp"
 #include "geom.hpp"
 
 namespace dgpyr {
@@ -196,6 +197,8 @@ __global__ __launch_bounds__(kThreads) void k_surface(const double* __restrict__
     const double J = pyr_jac(sX + le * 16, ops.na[i], ops.nb[i]);
     const double minv = 1.0 / (J * ops.wwc[i]);
     const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+    const double dte = dt * mesh.mat[e * 4 + 3];
+    acc[0] -= source_term<D::Np>(mesh, e, i);
     double rhs[4];
     rhs[0] = -kap * minv * acc[0];
 #pragma unroll
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_surface(const double* __restrict__
       double* r = R + e * 4 * D::Np;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const double rn = (ra == 0.0 ? 0.0 : ra * r[f * D::Np + i]) + dt * rhs[f];
+        const double rn = (ra == 0.0 ? 0.0 : ra * r[f * D::Np + i]) + dte * rhs[f];
         r[f * D::Np + i] = rn;
         o[f * D::Np + i] += rb * rn;
       }

@@ -78,6 +78,9 @@ __global__ __launch_bounds__(kBlock) void k_volume_mfma(const double* __restrict
       yr = M::mma(afr[c], DrF[fb + c * 64], yr);
       ys = M::mma(afr[c], DsF[fb + c * 64], ys);
       yt = M::mma(afr[c], DtF[fb + c * 64], yt);
+      // keep at most four chunks of operand loads in flight: hoisting all of
+      // them costs enough registers to halve the occupancy
+      if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     const int q = 16 * t + dq;
     double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0, Q3 = 0.0;
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
   }
   if (e >= mesh.K) return;
   const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+  const double dte = dt * mesh.mat[e * 4 + 3];
   const double* vo = vol + e * 4 * TT::Np;
 #pragma unroll
   for (int u = 0; u < TT::NIT; ++u) {
@@ -214,8 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t idx = (e * 4 + v) * TT::Np + i;
-      finish_coeff<MODE>(vo[v * TT::Np + i] + (double)z[u][v], minv, v == 0 ? kap : irho, out, R,
-                         idx, ra, rb, dt);
+      const double acc = vo[v * TT::Np + i] + (double)z[u][v] -
+                         (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);
+      finish_coeff<MODE>(acc, minv, v == 0 ? kap : irho, out, R, idx, ra, rb, dte);
     }
   }
 }
@@ -268,6 +273,9 @@ __global__ __launch_bounds__(kBlock) void k_stage_mfma(const double* __restrict_
       yr = M::mma(afr[c], DrF[fb + c * 64], yr);
       ys = M::mma(afr[c], DsF[fb + c * 64], ys);
       yt = M::mma(afr[c], DtF[fb + c * 64], yt);
+      // keep at most four chunks of operand loads in flight: hoisting all of
+      // them costs enough registers to halve the occupancy
+      if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     const int q = 16 * t + dq;
     double Q[4] = {0.0, 0.0, 0.0, 0.0};
@@ -324,15 +332,18 @@ __global__ __launch_bounds__(kBlock) void k_stage_mfma(const double* __restrict_
   // inverse mass, material, RK stage (Algorithm 3)
   if (e >= mesh.K) return;
   const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+  const double dte = dt * mesh.mat[e * 4 + 3];
 #pragma unroll
   for (int u = 0; u < TT::NIT; ++u) {
     const int i = 16 * u + dq;
     if (i >= TT::Np) continue;
     const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      finish_coeff<MODE>((double)z[u][v], minv, v == 0 ? kap : irho, out, R,
-                         (e * 4 + v) * TT::Np + i, ra, rb, dt);
+    for (int v = 0; v < 4; ++v) {
+      const double acc = (double)z[u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);
+      finish_coeff<MODE>(acc, minv, v == 0 ? kap : irho, out, R, (e * 4 + v) * TT::Np + i, ra,
+                         rb, dte);
+    }
   }
 }
 

@@ -312,10 +312,12 @@ __global__ __launch_bounds__(kThreads) void k_stage_sf(const double* __restrict_
     const double* xv = sX + le * 16;
     const double minv = 1.0 / (pyr_jac(xv, ops.na[n], ops.nb[n]) * ops.wwc[n]);
     const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+    const double dte = dt * mesh.mat[e * 4 + 3];
+    acc[0] -= source_term<Np>(mesh, e, n);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       finish_coeff<MODE>(acc[v], minv, v == 0 ? kap : irho, out, R, (e * 4 + v) * Np + n, ra, rb,
-                         dt);
+                         dte);
   }
 }
 

@@ -271,3 +271,43 @@ def test_eigenmode_convergence_rate(N):
     rate = np.log2(errs[-2] / errs[-1])
     assert prate > N + 1 - 0.15, (perr, prate)
     assert rate > N + 0.5, (errs, rate)
+
+
+def test_ricker_closed_form():
+    from oracle.dg import ricker
+    f0 = 10.0
+    assert abs(ricker(0.1, f0) - 1.0) < 1e-15            # peak at t = 1/f0
+    z = 1.0 / (np.sqrt(2.0) * np.pi * f0)                # zero crossings
+    assert abs(ricker(0.1 + z, f0)) < 1e-15 and abs(ricker(0.1 - z, f0)) < 1e-15
+
+
+def test_point_location_inverts_the_map():
+    from oracle.dg import locate_point
+    from oracle.geometry import map_points
+    verts = warped_pyramid(0.7)[0]
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a, b, c = rng.uniform(-0.95, 0.95, 3)
+        r, s, t = collapse(np.array([a]), np.array([b]), np.array([c]))
+        x = map_points(verts[None], r, s, t)[0, 0]
+        rst, inside = locate_point(verts, x)
+        assert inside and np.allclose(rst, [r[0], s[0], t[0]], atol=1e-12)
+
+
+def test_point_source_pairs_with_constant():
+    """b_i = R(t) phi_i(xi): against the coefficients w of the constant 1 (which
+    satisfy sum_i w_i phi_i = 1), w.b = R(t) -- the source injects R(t) of
+    'volume' into int p / kappa.  Checked through dE-type pairing
+    sum_i w_i (M dp/dt)_i / kappa = R(t) for U = 0 (no other terms)."""
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    N, f0, t = 3, 10.0, 0.093
+    src = [dict(x=[0.41, 0.37, 0.62], f0=f0)]
+    kap = np.full(48, 1.7)
+    dg = AcousticDG(xyz, e2v, N, kappa=kap, sources=src)
+    assert len(dg.sources) == 1
+    out = dg.rhs(np.zeros((48, 4, dg.Np)), t=t)
+    one = dg.project(lambda X, tt: np.ones((X.shape[0], 4)), xyz, e2v)[:, 0]  # coefficients of 1
+    Mdp = np.einsum("eij,ej->ei", dg.M, out[:, 0]) / kap[:, None]
+    from oracle.dg import ricker
+    assert abs(np.sum(one * Mdp) - ricker(t, f0)) < 1e-12
+    assert np.abs(out[:, 1:]).max() == 0.0
