@@ -73,6 +73,13 @@ typedef struct {
   const double* rho;    /* [nelems] density, or NULL for 1                         */
   const double* kappa;  /* [nelems] bulk modulus, or NULL for 1                    */
   int32_t bc;           /* dgpyr_bc, applied on every face without a neighbour    */
+  int32_t nsources;     /* number of point sources (0 = none)                      */
+  const double* sources;/* [nsources][6]: x, y, z, amplitude, f0, delay; source s
+                           adds amplitude R(t) delta(x - x_s) to the pressure
+                           equation (the right-hand side f of Section 4.3), with
+                           the Ricker wavelet R(t) = (1 - 2 a) exp(-a),
+                           a = (pi f0 (t - delay))^2 (delay <= 0 means 1/f0).  At
+                           most one source per element.                          */
 } dgpyr_mesh;
 
 /* dgpyr_opts.flags bits */
@@ -82,7 +89,10 @@ typedef struct {
                                            launches instead of one fused stage kernel */
 #define DGPYR_FLAG_SUM_FACTORIZED 4u    /* FP64 sum-factorised evaluation of the same
                                            contractions through the collapsed tensor
-                                           structure of the basis (Section 4.4), fused */
+                                           structure of the basis (Section 4.4), fused;
+                                           setup returns E_UNSUPPORTED unless the
+                                           library was built with
+                                           DGPYR_ENABLE_SUM_FACTORIZED          */
 
 typedef struct {
   int32_t precision; /* dgpyr_precision                                           */

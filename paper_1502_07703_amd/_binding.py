@@ -39,6 +39,8 @@ class Mesh(ctypes.Structure):
         ("rho", POINTER(c_double)),
         ("kappa", POINTER(c_double)),
         ("bc", c_int32),
+        ("nsources", c_int32),
+        ("sources", POINTER(c_double)),
     ]
 
 

@@ -34,6 +34,21 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 136
                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
 
+// Stage times c_s of the scheme: the value of U at the start of stage s when
+// integrating U' = 1 from 0 with dt = 1 (consistent with A, B to the last bit).
+struct StageTimes {
+  double c[5];
+  StageTimes() {
+    double u = 0.0, r = 0.0;
+    for (int s = 0; s < 5; ++s) {
+      c[s] = u;
+      r = kRkA[s] * r + 1.0;
+      u += kRkB[s] * r;
+    }
+  }
+};
+const StageTimes kRkC;
+
 template <typename T>
 dgpyr_status upload(dgpyr_ctx* c, const std::vector<T>& h, const T** out, const char* what) {
   void* p = nullptr;
@@ -319,9 +334,15 @@ const char* dgpyr_status_string(dgpyr_status s) {
 
 const char* dgpyr_last_error(void) { return g_err.c_str(); }
 
-dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts, void* stream,
-                         dgpyr_ctx** out) {
-  (void)stream;
+}  // extern "C"
+
+namespace {
+
+// Setup shared by dgpyr_setup and the batch: dtscale (optional, [K]) is the
+// per-element time-step scale; src_range (optional) limits each source's
+// element search.
+dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts,
+                        const double* dtscale, const int64_t* src_range, dgpyr_ctx** out) {
   if (!out) return fail(DGPYR_E_ARG, "out is null");
   *out = nullptr;
   if (!mesh || !opts) return fail(DGPYR_E_ARG, "mesh or opts is null");
@@ -336,6 +357,13 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   if ((opts->flags & DGPYR_FLAG_SUM_FACTORIZED) &&
       (opts->precision != DGPYR_FP64 || (opts->flags & (DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED))))
     return fail(DGPYR_E_UNSUPPORTED, "the sum-factorised kernels are FP64 and fused only");
+#ifndef DGPYR_ENABLE_SUM_FACTORIZED
+  // The sum-factorised kernels are held back from device runs until a device
+  // fault seen in a run that included them is explained; they are built and
+  // checked only in the CPU emulation build, which defines this macro.
+  if (opts->flags & DGPYR_FLAG_SUM_FACTORIZED)
+    return fail(DGPYR_E_UNSUPPORTED, "the sum-factorised kernels are disabled in this build");
+#endif
   if (!(opts->alpha >= 0.0)) return fail(DGPYR_E_ARG, "alpha must be >= 0");
   if (opts->precision != DGPYR_FP64 && opts->precision != DGPYR_FP32_MFMA &&
       opts->precision != DGPYR_SPLIT_BF16)
@@ -361,6 +389,19 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
     free_ctx(c);
     return fail((dgpyr_status)rc, err);
   }
+  if (mesh->nsources < 0 || (mesh->nsources > 0 && !mesh->sources)) {
+    free_ctx(c);
+    return fail(DGPYR_E_ARG, "bad source list");
+  }
+  if (mesh->nsources > 0) {
+    rc = dgpyr::locate_sources(ops, mesh->nsources, mesh->sources, src_range, md, err);
+    if (rc != 0) {
+      free_ctx(c);
+      return fail((dgpyr_status)rc, err);
+    }
+  }
+  if (dtscale)
+    for (int64_t e = 0; e < md.K; ++e) md.mat[4 * e + 3] = dtscale[e];
   c->N = N;
   c->Np = ops.Np;
   c->Nc = ops.Nc;
@@ -416,6 +457,18 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
   if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
   if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
+  if (st == DGPYR_OK && md.nsrc > 0) {
+    c->nsrc = md.nsrc;
+    st = upload(c, md.src_of, &c->mesh.src_of, "src_of");
+    if (st == DGPYR_OK) st = upload(c, md.src_phi, &c->mesh.src_phi, "src_phi");
+    if (st == DGPYR_OK) st = upload(c, md.src_par, &c->mesh.src_par, "src_par");
+  }
+  if (st == DGPYR_OK) {
+    std::vector<double> zero(2, 0.0);
+    const double* pc = nullptr;
+    st = upload(c, zero, &pc, "clock");
+    c->clock = const_cast<double*>(pc);
+  }
   if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->T, "trace buffer");
   if (st == DGPYR_OK && (c->reference_kernels || c->unfused))
     st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->vol, "volume buffer");
@@ -428,6 +481,16 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
   c->mesh.alpha = c->alpha;
   *out = c;
   return DGPYR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts, void* stream,
+                         dgpyr_ctx** out) {
+  (void)stream;
+  return setup_impl(mesh, N, opts, nullptr, nullptr, out);
 }
 
 dgpyr_status dgpyr_get_info(const dgpyr_ctx* c, dgpyr_info* info) {
@@ -464,34 +527,44 @@ dgpyr_status dgpyr_unpack(dgpyr_ctx* c, const double* U, double* canon, void* st
 }
 
 dgpyr_status dgpyr_rhs(dgpyr_ctx* c, const double* U, double* dUdt, double t, void* stream) {
-  (void)t;
   if (dgpyr_status s = check_ctx(c)) return s;
   if (!U || !dUdt) return fail(DGPYR_E_ARG, "null array");
   if ((const double*)dUdt == U) return fail(DGPYR_E_ARG, "U and dUdt must not alias");
+  c->mesh.clock = nullptr;
+  c->mesh.t_base = t;
+  c->mesh.c_stage = 0.0;
+  c->mesh.dt_time = 0.0;
   hipError_t e = run_stage(c, 0, U, dUdt, nullptr, 0.0, 0.0, 0.0, (hipStream_t)stream, nullptr);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "rhs launch");
 }
 
 dgpyr_status dgpyr_step(dgpyr_ctx* c, double* U, double* R, double t0, double dt, int32_t nsteps,
                         void* stream) {
-  (void)t0;
   if (dgpyr_status s = check_ctx(c)) return s;
   if (!U || !R) return fail(DGPYR_E_ARG, "null array");
   if (U == R) return fail(DGPYR_E_ARG, "U and R must not alias");
   if (nsteps < 0) return fail(DGPYR_E_ARG, "nsteps must be >= 0");
   hipStream_t s = (hipStream_t)stream;
-  for (int n = 0; n < nsteps; ++n)
+  hipError_t e = dgpyr::launch_clock(c->clock, 0.0, false, s);
+  if (e != hipSuccess) return hip_fail(e, "clock");
+  c->mesh.clock = c->clock;
+  c->mesh.t_base = t0;
+  c->mesh.dt_time = dt;
+  for (int n = 0; n < nsteps; ++n) {
     for (int st = 0; st < 5; ++st) {
-      hipError_t e = run_stage(c, 1, U, U, R, kRkA[st], kRkB[st], dt, s, nullptr);
+      c->mesh.c_stage = kRkC.c[st];
+      e = run_stage(c, 1, U, U, R, kRkA[st], kRkB[st], dt, s, nullptr);
       if (e != hipSuccess) return hip_fail(e, "step launch");
     }
+    e = dgpyr::launch_clock(c->clock, 1.0, true, s);
+    if (e != hipSuccess) return hip_fail(e, "clock");
+  }
   return DGPYR_OK;
 }
 
 dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, double dt,
                               int32_t nsteps, void* stream, int32_t nk, double* kernel_ms,
                               int64_t* launches) {
-  (void)t0;
   if (dgpyr_status s = check_ctx(c)) return s;
   if (!U || !R) return fail(DGPYR_E_ARG, "null array");
   if (U == R) return fail(DGPYR_E_ARG, "U and R must not alias");
@@ -504,11 +577,20 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, dou
   hipStream_t s = (hipStream_t)stream;
   LaunchTimer tm(s, nk, kernel_ms, launches);
   if (tm.err != hipSuccess) return hip_fail(tm.err, "event create");
-  for (int n = 0; n < nsteps; ++n)
+  hipError_t ec = dgpyr::launch_clock(c->clock, 0.0, false, s);
+  if (ec != hipSuccess) return hip_fail(ec, "clock");
+  c->mesh.clock = c->clock;
+  c->mesh.t_base = t0;
+  c->mesh.dt_time = dt;
+  for (int n = 0; n < nsteps; ++n) {
     for (int st = 0; st < 5; ++st) {
+      c->mesh.c_stage = kRkC.c[st];
       hipError_t e = run_stage(c, 1, U, U, R, kRkA[st], kRkB[st], dt, s, &tm);
       if (e != hipSuccess) return hip_fail(e, "step launch");
     }
+    ec = dgpyr::launch_clock(c->clock, 1.0, true, s);
+    if (ec != hipSuccess) return hip_fail(ec, "clock");
+  }
   tm.drain();
   if (tm.err != hipSuccess) return hip_fail(tm.err, "event timing");
   hipError_t e = hipStreamSynchronize(s);

@@ -81,14 +81,17 @@ struct DevMesh {
   int bc;
   double alpha;
   // Point sources (Section 4.3 right-hand side b): src_of[e] is the source
-  // index of element e or -1; src_phi [nsrc][Np] = phi_i(xi_s);
-  // src_par [nsrc][4] = amplitude, f0, delay, 0.  The stage time of element e
-  // is t_base + t_tau * mat[e][3].
+  // index of element e or -1 (NULL: no sources); src_phi [nsrc][Np] =
+  // phi_i(xi_s); src_par [nsrc][4] = amplitude, f0, delay, 0.  The stage time
+  // of element e is t_base + (clock[0] + c_stage) * dt_time * mat[e][3], with
+  // clock the device step counter (NULL reads as 0).
   const int* src_of;
   const double* src_phi;
   const double* src_par;
+  const double* clock;
   double t_base;
-  double t_tau;
+  double c_stage;
+  double dt_time;
 };
 
 }  // namespace dgpyr
@@ -112,6 +115,8 @@ struct dgpyr_ctx {
   const double* xc = nullptr;      // [N+1] Gauss-Jacobi(2,0) nodes in c
   double* T = nullptr;    // [K][Nfc][4] face traces
   double* vol = nullptr;  // [K][4][Np] volume contribution
+  double* clock = nullptr;  // device step counter (source times)
+  int nsrc = 0;
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
 };
@@ -126,6 +131,7 @@ hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const d
                           double* out, double* R, double ra, double rb, double dt, hipStream_t s);
 // Initial data and evaluation (kernels_aux.hip).
 hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s);
+hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s);
 hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s);
 hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s);
 // Matrix-core kernels (kernels_mfma.hip).

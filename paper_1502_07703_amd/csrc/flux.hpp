@@ -73,7 +73,8 @@ __device__ __forceinline__ double source_term(const DevMesh& mesh, int64_t e, in
   const int s = mesh.src_of[e];
   if (s < 0) return 0.0;
   const double* par = mesh.src_par + 4 * s;
-  const double t = mesh.t_base + mesh.t_tau * mesh.mat[e * 4 + 3];
+  const double n = mesh.clock ? mesh.clock[0] : 0.0;
+  const double t = mesh.t_base + (n + mesh.c_stage) * mesh.dt_time * mesh.mat[e * 4 + 3];
   return par[0] * ricker_wavelet(t, par[1], par[2]) * mesh.src_phi[(int64_t)s * Np + i];
 }
 

@@ -23,7 +23,19 @@ struct MeshData {
   std::vector<double> mat;
   double inv_length_max = 0.0;  // max_K c_K |dK| / |K|
   bool hex_groups = false;
+  // point sources: src_of [K] (-1 = none), src_phi [nsrc][Np], src_par [nsrc][4]
+  std::vector<int32_t> src_of;
+  std::vector<double> src_phi, src_par;
+  int nsrc = 0;
 };
+
+// Locates each source point (x, y, z, amplitude, f0, delay) in the lowest-index
+// element containing it (Newton iteration on the collapsed vertex map) and
+// evaluates the basis there.  Points outside every element are an error.
+// range (optional, [nsrc][2]) limits the search of source s to elements
+// range[2s] <= e < range[2s+1].
+int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t* range,
+                   MeshData& md, std::string& err);
 
 // Returns 0 on success or a negative dgpyr_status with a message in err.
 int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nelems,

@@ -132,6 +132,11 @@ struct BasisEval {
 
 }  // namespace
 
+void eval_basis(int N, double a, double b, double c, double* v) {
+  BasisEval be(N);
+  be.eval(a, b, c, v, nullptr, nullptr, nullptr);
+}
+
 bool build_refops(int N, RefOps& o, char* msg, int msglen) {
   o.N = N;
   o.Np = n_basis(N);

@@ -58,6 +58,9 @@ struct RefOps {
   std::vector<double> sfGf;  // [m][k] g_k(xt[m])
 };
 
+// Values of all Np basis functions of degree N at collapsed (a, b, c).
+void eval_basis(int N, double a, double b, double c, double* v);
+
 // Builds all reference data; returns false (with a message) if an internal
 // consistency check fails (Lemma 2 constant, reference mass diagonality).
 bool build_refops(int N, RefOps& ops, char* msg, int msglen);

@@ -62,9 +62,19 @@ __global__ void k_eval(DevOps ops, int64_t K, int Np, int Nc, const double* __re
   f[gid] = acc;
 }
 
+// Step counter used for source times: set or advance by one (one thread).
+__global__ void k_clock(double* clock, double value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = add ? clock[0] + value : value;
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s) {
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, clock, value, add ? 1 : 0);
+  return hipGetLastError();
+}
 
 hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s) {
   hipLaunchKernelGGL(k_points, dim3(nblocks(c.K * c.Nc)), dim3(kThreads), 0, s, c.ops, c.mesh,

@@ -4,12 +4,12 @@ precision form's error against the FP64 path (Section 4.3 experiments)."""
 import numpy as np
 import pytest
 
-from gpu_helpers import log, rel_err_per_field
+from gpu_helpers import HELD_BACK, log, rel_err_per_field
 from oracle import AcousticDG, lsrk_run
 from oracle.dg import wall_mode
 from synth import hex_pyramid_mesh
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, HELD_BACK]
 
 
 def _mode_torch(m):
