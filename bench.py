@@ -65,6 +65,38 @@ def stage_work(N: int):
     return F, B
 
 
+TRAFFIC_SOURCES = ("context.hpp", "flux.hpp", "geom.hpp", "kernels_mfma.hip", "mfma.hpp")
+
+
+def kernel_sources_digest():
+    """SHA-256 over the device sources that define the matrix-core kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1502_07703_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (copy-calibrated) for this kernel and workload, or None when no record
+    exists or the kernel sources changed since the counters were taken."""
+    import glob
+    digest = kernel_sources_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record:"):
+                    continue
+                rec = json.loads(line.split(":", 1)[1])
+                if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                        and rec.get("sources_sha256") == digest):
+                    return int(rec["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(xyz, e2v, N, U, nsample, reps=3):
     """The oracle's right-hand side on a seeded sample of elements, one thread."""
     from threadpoolctl import threadpool_limits
@@ -166,18 +198,21 @@ def main():
                        "tflops": F * K / (avg * 1e-3) / 1e12,
                        "gbs": Bb * K / (avg * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    path_key = ("reference" if args.reference_kernels else "sumfact" if args.sum_factorized
+                else "unfused" if args.unfused else "fused")
+    traffic = recorded_traffic(dom, f"k1d={args.k1d} N={N} {args.precision} {path_key}")
     Fd, Bd = kernel_work(dom, N)
     t_d = kernels[dom]["avg_ms"] * 1e-3
     compute_bound = Fd / (PEAK_FP64_TFLOPS * 1e12) >= Bd / (PEAK_HBM_GBS * 1e9)
     if compute_bound:
         ach = Fd * K / t_d / 1e12
         roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
+                "frac": ach / PEAK_FP64_TFLOPS, "traffic": traffic, "kernel": dom,
                 "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
     else:
         ach = Bd * K / t_d / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
+                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "kernel": dom,
                 "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
     Fs, Bs = stage_work(N)
     t_stage = wall / stages

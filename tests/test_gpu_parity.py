@@ -192,7 +192,6 @@ def test_rhs_fp32_mfma_form(N):
     assert np.any(err > 1e-10), "FP32 form gave FP64-accurate results: wrong kernels?"
 
 
-@HELD_BACK
 @pytest.mark.parametrize("N", [2, 6])
 def test_rhs_parity_unfused_matrix_core(N):
     """Separate matrix-core volume and surface launches (flag) meet the same bar."""
@@ -205,7 +204,6 @@ def test_rhs_parity_unfused_matrix_core(N):
     assert np.all(rel_err_per_field(got, ref) < TOL)
 
 
-@HELD_BACK
 @pytest.mark.parametrize("N", [2, 4, 7])
 def test_rhs_split_bf16_form(N):
     """Split-BF16 matrix-core contractions (three bf16 products per multiply, FP32
