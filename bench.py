@@ -5,9 +5,14 @@ One bench step is one LSRK(5,4) time step: five stages, each a full
 right-hand side (trace, volume, surface + lift, inverse mass) and the RK
 update, over every element of the mesh.  Default workload: the unit cube as
 40^3 perturbed hexahedra x 6 = 384 000 pyramids, N = 4 (Np = 55), four fields,
-c = 1, wall boundaries, penalty flux; synthetic seeded mesh and state.
+c = 1, wall boundaries, penalty flux; synthetic seeded mesh; initial data the
+L2-projected wall eigenmode cos(pi x) cos(pi y) cos(pi z); 200 timed steps.
 
-Prints one JSON line.  ``value`` is GDOF.stages/s = 4 Np K * 5 * steps / t.
+Prints one JSON line.  ``value`` is GDOF.stages/s = 4 Np K * 5 * steps / t for
+the FP64 path.  The same line carries the L2 error against the exact mode at
+the final time and, for the FP32-MFMA and split-BF16 forms run on the same
+workload, initial data and step count, their throughput, speedup and L2
+errors (equal error: within 10 % of the FP64 error).
 """
 
 from __future__ import annotations
@@ -29,6 +34,7 @@ METRIC = "GDOF·stages/s, FP64 plain vs FP32-MFMA form at equal L2 error, N=3–
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 
 
 def n_basis(N):
@@ -97,6 +103,29 @@ def recorded_traffic(kernel: str, workload: str):
     return None
 
 
+def wall_mode_values(P, m, t):
+    """Exact wall eigenmode of the unit cube, (p, u, v, w) at points P (K, Nc, 3)
+    as a (K, 4, Nc) tensor: p = C cos(w t), u = sin(w t)/sqrt(3) grad-like terms,
+    C = cos(m pi x) cos(m pi y) cos(m pi z), w = sqrt(3) m pi."""
+    import torch
+    k = m * np.pi
+    om = np.sqrt(3.0) * k
+    x, y, z = P[..., 0], P[..., 1], P[..., 2]
+    cx, cy, cz = torch.cos(k * x), torch.cos(k * y), torch.cos(k * z)
+    sx, sy, sz = torch.sin(k * x), torch.sin(k * y), torch.sin(k * z)
+    a = np.sin(om * t) / np.sqrt(3.0)
+    return torch.stack([cx * cy * cz * np.cos(om * t), a * sx * cy * cz, a * cx * sy * cz,
+                        a * cx * cy * sz], dim=1).contiguous()
+
+
+def l2_norm(solver, U, P, wJ, f=None):
+    """sqrt(sum_q w_q J_q |U(x_q) - f_q|^2) over all fields on the volume rule."""
+    import torch
+    vals = solver.evaluate(U)
+    d = vals if f is None else vals - f
+    return float(torch.sqrt((wJ[:, None, :] * d * d).sum()).item())
+
+
 def cpu_baseline(xyz, e2v, N, U, nsample, reps=3):
     """The oracle's right-hand side on a seeded sample of elements, one thread."""
     from threadpoolctl import threadpool_limits
@@ -119,6 +148,26 @@ def cpu_baseline(xyz, e2v, N, U, nsample, reps=3):
                       f"{reps}, BLAS limited to 1 thread, host {platform.processor() or platform.machine()}"}
 
 
+def timed_steps(dg, solver, U, R, t0, dt, nsteps, stream):
+    """nsteps LSRK steps through dgpyr_step_timed: wall seconds (bracketed by
+    device synchronisation) and per-kernel-kind HIP-event times."""
+    import ctypes
+
+    import torch
+    L = dg._binding.lib()
+    names = L.dgpyr_kernel_names(solver._h).decode().split(";")
+    nk = len(names)
+    ms = (ctypes.c_double * nk)()
+    cnt = (ctypes.c_int64 * nk)()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    st = L.dgpyr_step_timed(solver._h, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(R.data_ptr()),
+                            t0, dt, nsteps, ctypes.c_void_p(stream.cuda_stream), nk, ms, cnt)
+    dg._binding.check(st, "dgpyr_step_timed")
+    torch.cuda.synchronize()
+    return time.perf_counter() - w0, names, list(ms), list(cnt)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,9 +182,15 @@ def main():
                     help="separate matrix-core volume and surface launches")
     ap.add_argument("--sum-factorized", action="store_true",
                     help="FP64 sum-factorised kernels")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="4-element groups per wave of the fused matrix-core kernels "
+                         "(0 = library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 256 MiB buffer 3 times (a plain copy "
                          "of known size for scaling HBM counters)")
+    ap.add_argument("--mode", type=int, default=1, help="wall eigenmode number m of the initial data")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32-MFMA / split-BF16 comparison on the same workload")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -147,7 +202,7 @@ def main():
     import torch
 
     import paper_1502_07703_amd as dg
-    from synth import hex_pyramid_mesh, random_state
+    from synth import hex_pyramid_mesh
 
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -156,11 +211,13 @@ def main():
     Np = n_basis(N)
     xyz, e2v = hex_pyramid_mesh(args.k1d, seed=2)
     K = e2v.shape[0]
-    Uh = random_state(K, N, seed=11, scale=1e-3)
     solver = dg.Solver(xyz, e2v, N, precision=args.precision,
                        reference_kernels=args.reference_kernels, unfused=args.unfused,
-                       sum_factorized=args.sum_factorized)
-    U = solver.pack(torch.from_numpy(Uh).cuda())
+                       sum_factorized=args.sum_factorized, groups_per_wave=args.groups)
+    # initial data: the unit-cube wall eigenmode (mode m), L2-projected on the device
+    P, wJ = solver.volume_points()
+    U0 = solver.project(wall_mode_values(P, args.mode, 0.0))
+    U = U0.clone()
     R = solver.empty_state().zero_()
     dt = solver.stable_dt(0.5)
     stream = torch.cuda.current_stream()
@@ -168,22 +225,9 @@ def main():
     solver.step(U, R, dt, args.warmup)
     torch.cuda.synchronize()
 
-    names = dg._binding.lib().dgpyr_kernel_names(solver._h).decode().split(";")
-    import ctypes
-    nk = len(names)
-    ms = (ctypes.c_double * nk)()
-    cnt = (ctypes.c_int64 * nk)()
-
     # Timed region: K steps, each kernel launch bracketed by HIP events on the
     # launch stream; wall time bracketed by synchronisation.
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = dg._binding.lib().dgpyr_step_timed(solver._h, ctypes.c_void_p(U.data_ptr()),
-                                            ctypes.c_void_p(R.data_ptr()), 0.0, dt, args.steps,
-                                            ctypes.c_void_p(stream.cuda_stream), nk, ms, cnt)
-    dg._binding.check(st, "dgpyr_step_timed")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall, names, ms, cnt = timed_steps(dg, solver, U, R, args.warmup * dt, dt, args.steps, stream)
     if not torch.isfinite(U).all():
         print("non-finite state after the timed steps", file=sys.stderr)
         sys.exit(1)
@@ -200,14 +244,18 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     path_key = ("reference" if args.reference_kernels else "sumfact" if args.sum_factorized
                 else "unfused" if args.unfused else "fused")
-    traffic = recorded_traffic(dom, f"k1d={args.k1d} N={N} {args.precision} {path_key}")
+    groups = solver.info_groups()
+    traffic = recorded_traffic(dom, f"k1d={args.k1d} N={N} {args.precision} {path_key} g{groups}")
     Fd, Bd = kernel_work(dom, N)
     t_d = kernels[dom]["avg_ms"] * 1e-3
     compute_bound = Fd / (PEAK_FP64_TFLOPS * 1e12) >= Bd / (PEAK_HBM_GBS * 1e9)
     if compute_bound:
         ach = Fd * K / t_d / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_TFLOPS, "traffic": traffic, "kernel": dom,
+        matrix = not (args.reference_kernels or args.sum_factorized)
+        peak = {"fp64": PEAK_FP64_TFLOPS, "fp32_mfma": PEAK_FP32_TFLOPS,
+                "split_bf16": PEAK_BF16_TFLOPS}[args.precision]
+        roof = {"bound": "mfma" if matrix else "alu", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic, "kernel": dom,
                 "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
     else:
         ach = Bd * K / t_d / 1e9
@@ -239,6 +287,7 @@ def main():
                                f"N={N}, 4 fields, walls, penalty flux, LSRK(5,4)",
                    "k1d": args.k1d, "nelems": K, "N": N, "Np": Np, "dof": 4 * Np * K,
                    "precision": args.precision, "stages_per_step": 5, "dt": dt,
+                   "groups_per_wave": groups,
                    "kernels": ("reference (vector ALU)" if args.reference_kernels else
                                "sum-factorised, fused" if args.sum_factorized else
                                "matrix core, unfused" if args.unfused else "matrix core, fused")},
@@ -246,6 +295,31 @@ def main():
         "stage": whole,
         "kernels": kernels,
     }
+    # Error of the run against the exact mode at the final time, and the
+    # precision forms on the same workload, initial data and step count.
+    T_end = (args.warmup + args.steps) * dt
+    exact = wall_mode_values(P, args.mode, T_end)
+    e_main = l2_norm(solver, U, P, wJ, exact)
+    out["l2_error_vs_mode"] = {"mode": args.mode, "t": T_end, "value": e_main}
+    if (not args.no_forms and args.precision == "fp64" and not args.reference_kernels
+            and not args.sum_factorized and not args.unfused):
+        forms = {}
+        for form in ("fp32_mfma", "split_bf16"):
+            with dg.Solver(xyz, e2v, N, precision=form) as sf:
+                Uf = U0.clone()
+                Rf = sf.empty_state().zero_()
+                sf.step(Uf, Rf, dt, args.warmup)
+                wf, nf, msf, cf = timed_steps(dg, sf, Uf, Rf, args.warmup * dt, dt, args.steps,
+                                              stream)
+                e_f = l2_norm(sf, Uf, P, wJ, exact)
+                d_f = l2_norm(sf, Uf - U, P, wJ)
+                vf = 4 * Np * K * stages / wf / 1e9
+                forms[form] = {
+                    "value": vf, "speedup_vs_fp64": vf / value,
+                    "l2_error_vs_mode": e_f, "l2_diff_vs_fp64": d_f,
+                    "equal_error": abs(e_f - e_main) <= 0.1 * e_main,
+                    "kernels": {nm: {"avg_ms": msf[i] / max(cf[i], 1)} for i, nm in enumerate(nf)}}
+        out["precision_forms"] = forms
     if args.copy_calibration:
         nbytes = 256 << 20
         a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -255,7 +329,8 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(xyz, e2v, N, Uh, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(xyz, e2v, N, solver.unpack(U0).cpu().numpy(),
+                                           args.cpu_sample)
     solver.close()
     print(json.dumps(out), flush=True)
 

@@ -112,6 +112,9 @@ typedef struct {
   int32_t hex_groups;      /* 1 if elements come in groups of 6 sharing an apex    */
   int32_t precision;       /* precision form built                                 */
   int64_t device_bytes;    /* device memory held by the context                    */
+  int32_t groups_per_wave; /* 4-element groups per wave of the fused matrix-core
+                              kernels (dgpyr_set_groups)                         */
+  int32_t reserved;        /* 0                                                    */
 } dgpyr_info;
 
 typedef struct dgpyr_ctx dgpyr_ctx;
@@ -160,6 +163,15 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* ctx, double* U, double* R, double t0, d
 /* Semicolon-separated names of the kernel kinds dgpyr_step launches, in the
  * order used by dgpyr_step_timed; the string lives as long as the context. */
 const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
+
+/* Work shape of the fused matrix-core kernels (FP64 and FP32 forms, and
+ * their trace kernel): groups_per_wave = number of 4-element groups one wave
+ * owns, so that each operator fragment loaded feeds that many matrix-core
+ * products.  1 or 2; 0 restores the library's choice for the context's N.
+ * Results are identical up to the same rounding for every choice.  Takes
+ * effect at the next launch; not synchronised with work already queued.
+ * Errors: E_ARG for other values. */
+dgpyr_status dgpyr_set_groups(dgpyr_ctx* ctx, int32_t groups_per_wave);
 
 /* Host-only inspection of the reference data the library builds for degree N
  * (no device needed).  which: 0 volume weights [Nc]; 1 V [Nc][Np];

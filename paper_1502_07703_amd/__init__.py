@@ -49,7 +49,7 @@ class Solver:
 
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
                  precision="fp64", reference_kernels=False, unfused=False,
-                 sum_factorized=False, stream=None):
+                 sum_factorized=False, groups_per_wave=0, stream=None):
         L = B.lib()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._e2v = np.ascontiguousarray(e2v, dtype=np.int64)
@@ -85,6 +85,8 @@ class Solver:
         self.info = {k: getattr(info, k) for k, _ in B.Info._fields_}
         self.N, self.Np, self.K = info.N, info.Np, info.nelems
         self.state_len, self.canon_len = info.state_len, info.canon_len
+        if groups_per_wave:
+            self.set_groups(groups_per_wave)
 
     # -- state helpers -----------------------------------------------------------
     def empty_state(self):
@@ -150,6 +152,16 @@ class Solver:
                                    _dptr(out, self.K * 4 * self.info["Nc"], "f"),
                                    _stream_handle(stream)), "dgpyr_eval")
         return out
+
+    def set_groups(self, groups_per_wave: int):
+        """Element groups per wave of the fused matrix-core kernels (0 = default)."""
+        B.check(B.lib().dgpyr_set_groups(self._h, int(groups_per_wave)), "dgpyr_set_groups")
+
+    def info_groups(self) -> int:
+        """Element groups per wave currently in effect."""
+        info = B.Info()
+        B.check(B.lib().dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
+        return int(info.groups_per_wave)
 
     def stable_dt(self, cfl=0.5):
         """CFL / (2(N+1)(N+3)/3 * max_K c_K |dK|/|K|) (Section 4.3 scaling)."""

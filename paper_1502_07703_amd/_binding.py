@@ -24,7 +24,7 @@ FLAG_SUM_FACTORIZED = 4
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
-    "dgpyr_step", "dgpyr_step_timed", "dgpyr_kernel_names", "dgpyr_host_reference",
+    "dgpyr_step", "dgpyr_step_timed", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
     "dgpyr_host_mesh", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
 )
@@ -53,7 +53,7 @@ class Info(ctypes.Structure):
         ("N", c_int32), ("Np", c_int32), ("Nc", c_int32), ("Nfc", c_int32),
         ("nelems", c_int64), ("state_len", c_int64), ("canon_len", c_int64),
         ("inv_length_max", c_double), ("hex_groups", c_int32), ("precision", c_int32),
-        ("device_bytes", c_int64),
+        ("device_bytes", c_int64), ("groups_per_wave", c_int32), ("reserved", c_int32),
     ]
 
 
@@ -90,6 +90,8 @@ def lib():
     L.dgpyr_step_timed.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32,
                                    c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]
     L.dgpyr_step_timed.restype = c_int32
+    L.dgpyr_set_groups.argtypes = [c_void_p, c_int32]
+    L.dgpyr_set_groups.restype = c_int32
     L.dgpyr_kernel_names.argtypes = [c_void_p]
     L.dgpyr_kernel_names.restype = c_char_p
     L.dgpyr_host_reference.argtypes = [c_int32, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]

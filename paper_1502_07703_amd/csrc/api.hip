@@ -134,6 +134,13 @@ struct LaunchTimer {
   }
 };
 
+// Default 4-element groups per wave of the fused matrix-core kernels.
+int default_groups(int N, int precision) {
+  (void)N;
+  (void)precision;
+  return 1;
+}
+
 // Kernel kinds per path, in dgpyr_step_timed order.
 const char* kNamesFused = "trace;stage";
 const char* kNamesSplit = "trace;volume;surface_update";
@@ -416,6 +423,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   c->reference_kernels = (opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) != 0;
   c->unfused = (opts->flags & DGPYR_FLAG_UNFUSED) != 0;
   c->sum_factorized = (opts->flags & DGPYR_FLAG_SUM_FACTORIZED) != 0;
+  c->mfma_groups = default_groups(N, opts->precision);
 
   std::vector<int> perm((size_t)10 * ops.Nfq);
   for (int o = 0; o < 8; ++o) dgpyr::quad_perm(N, o, &perm[(size_t)o * ops.Nfq]);
@@ -507,6 +515,8 @@ dgpyr_status dgpyr_get_info(const dgpyr_ctx* c, dgpyr_info* info) {
   info->hex_groups = c->hex_groups ? 1 : 0;
   info->precision = c->precision;
   info->device_bytes = c->device_bytes;
+  info->groups_per_wave = c->mfma_groups;
+  info->reserved = 0;
   return DGPYR_OK;
 }
 
@@ -595,6 +605,13 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, dou
   if (tm.err != hipSuccess) return hip_fail(tm.err, "event timing");
   hipError_t e = hipStreamSynchronize(s);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "stream synchronize");
+}
+
+dgpyr_status dgpyr_set_groups(dgpyr_ctx* c, int32_t groups) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (groups < 0 || groups > 2) return fail(DGPYR_E_ARG, "groups_per_wave must be 0, 1 or 2");
+  c->mfma_groups = groups == 0 ? default_groups(c->N, c->precision) : groups;
+  return DGPYR_OK;
 }
 
 const char* dgpyr_kernel_names(const dgpyr_ctx* c) {

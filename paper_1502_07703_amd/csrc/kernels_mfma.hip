@@ -17,6 +17,16 @@ constexpr int kEW = 4;                 // elements per wave
 constexpr int kEB = kWaves * kEW;      // elements per workgroup
 constexpr int kBlock = 64 * kWaves;
 
+// Orders this wave's LDS writes before its later LDS reads (and reads before
+// later writes).  A wave's LDS operations complete in issue order, so data
+// exchanged between lanes of one wave needs no workgroup barrier; the fences
+// keep the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // A operands of U for this wave: lane l holds U[e][f][4c + l/16] with (e, f)
 // the element and field of row l % 16 in the form's row order; zero beyond Np
 // or beyond the mesh.
@@ -132,29 +142,40 @@ __global__ __launch_bounds__(kBlock) void k_volume_mfma(const double* __restrict
 }
 
 // Trace interpolation U^f = V^f U at every face point (FP64 in every form:
-// jumps of traces are differences of O(1) values).  Lane l ends with all four
-// fields of element l/16 at face point 16t + l%16 and stores them as one
-// 32-byte vector into T[K][Nfc][4].
-template <int N>
+// jumps of traces are differences of O(1) values).  A wave owns G groups of 4
+// elements; each operator fragment loaded feeds G matrix-core products.  Lane
+// l ends with all four fields of element 4g + l/16 at face point 16t + l%16
+// and stores them as one 32-byte vector into T[K][Nfc][4].
+template <int N, int G>
 __global__ __launch_bounds__(kBlock) void k_trace_mfma(const double* __restrict__ U,
                                                        double* __restrict__ T, FragOps fo,
                                                        int64_t K) {
   using TT = Tiles<N>;
   using M = Mma<0>;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t ew0 = (int64_t)blockIdx.x * kEB + wv * kEW;
-  double afr[TT::NCH];
-  load_u_frags<N, 0>(U, ew0, K, lane, afr);
+  const int64_t ew0 = (int64_t)blockIdx.x * (kEB * G) + wv * (kEW * G);
+  double afr[G][TT::NCH];
+#pragma unroll
+  for (int g = 0; g < G; ++g) load_u_frags<N, 0>(U, ew0 + kEW * g, K, lane, afr[g]);
   const double* VfF = static_cast<const double*>(fo.VfF) + lane;
   const int de = lane >> 4, dq = lane & 15;
-  const int64_t e = ew0 + de;
   for (int t = 0; t < TT::NTF; ++t) {
-    M::Acc y = M::zero();
+    M::Acc y[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) y[g] = M::zero();
     const size_t fb = (size_t)t * TT::NCH * 64;
 #pragma unroll
-    for (int c = 0; c < TT::NCH; ++c) y = M::mma(afr[c], VfF[fb + c * 64], y);
+    for (int c = 0; c < TT::NCH; ++c) {
+      const double b = VfF[fb + c * 64];
+#pragma unroll
+      for (int g = 0; g < G; ++g) y[g] = M::mma(afr[g][c], b, y[g]);
+    }
     const int q = 16 * t + dq;
-    if (e < K && q < TT::Nfc) *reinterpret_cast<dx4*>(T + (e * TT::Nfc + q) * 4) = y;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t e = ew0 + kEW * g + de;
+      if (e < K && q < TT::Nfc) *reinterpret_cast<dx4*>(T + (e * TT::Nfc + q) * 4) = y[g];
+    }
   }
 }
 
@@ -228,27 +249,33 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 // Fused stage: volume term and surface lift accumulate into the same
 // matrix-core accumulators, then inverse mass, material and the RK stage are
 // applied in the epilogue; the volume contribution never leaves registers.
-// In RK mode the kernel reads and writes only its own elements' U and R;
-// other workgroups read traces (T), never U, so in-place update is safe.
-template <int N, int FORM, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stage_mfma(const double* __restrict__ U,
+// A wave owns G groups of 4 elements: every operator fragment loaded feeds G
+// products.  The D -> A layout changes go through a per-wave LDS tile and need
+// only wave-local ordering.  In RK mode the kernel reads and writes only its
+// own elements' U and R; other workgroups read traces (T), never U, so the
+// in-place update is safe.
+template <int N, int FORM, int MODE, int G>
+__global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restrict__ U,
                                                        const double* __restrict__ T, FragOps fo,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {
   using TT = Tiles<N>;
   using M = Mma<FORM>;
   using TV = typename M::T;
-  __shared__ double sX[kEB][16];
-  __shared__ TV sQ[kWaves][16][17];
+  constexpr int EW = kEW * G;      // elements per wave
+  constexpr int EB = kWaves * EW;  // elements per workgroup
+  __shared__ double sX[EB][16];
+  __shared__ TV sQ[kWaves][G][16][17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t eb0 = (int64_t)blockIdx.x * kEB;
-  for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
+  const int64_t eb0 = (int64_t)blockIdx.x * EB;
+  for (int x = threadIdx.x; x < EB * 16; x += kBlock) {
     const int64_t e = eb0 + x / 16;
     sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
   }
-  const int64_t ew0 = eb0 + wv * kEW;
-  TV afr[TT::NCH];
-  load_u_frags<N, FORM>(U, ew0, mesh.K, lane, afr);
+  const int64_t ew0 = eb0 + wv * EW;
+  TV afr[G][TT::NCH];
+#pragma unroll
+  for (int g = 0; g < G; ++g) load_u_frags<N, FORM>(U, ew0 + kEW * g, mesh.K, lane, afr[g]);
   __syncthreads();
 
   const TV* DrF = static_cast<const TV*>(fo.DrF) + lane;
@@ -258,105 +285,142 @@ __global__ __launch_bounds__(kBlock) void k_stage_mfma(const double* __restrict_
   const TV* LfF = static_cast<const TV*>(fo.LfF) + lane;
   const int de = lane >> 4, dq = lane & 15;
   const int row = lane & 15, kq = lane >> 4;
-  const int64_t e = ew0 + de;
-  const double* xv = sX[wv * kEW + de];
-  typename M::Acc z[TT::NIT];
+  typename M::Acc z[G][TT::NIT];
 #pragma unroll
-  for (int u = 0; u < TT::NIT; ++u) z[u] = M::zero();
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int u = 0; u < TT::NIT; ++u) z[g][u] = M::zero();
 
   // volume (Algorithm 1)
   for (int t = 0; t < TT::NTC; ++t) {
-    typename M::Acc yr = M::zero(), ys = M::zero(), yt = M::zero();
+    typename M::Acc yr[G], ys[G], yt[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) yr[g] = ys[g] = yt[g] = M::zero();
     const size_t fb = (size_t)t * TT::NCH * 64;
 #pragma unroll
     for (int c = 0; c < TT::NCH; ++c) {
-      yr = M::mma(afr[c], DrF[fb + c * 64], yr);
-      ys = M::mma(afr[c], DsF[fb + c * 64], ys);
-      yt = M::mma(afr[c], DtF[fb + c * 64], yt);
-      // keep at most four chunks of operand loads in flight: hoisting all of
+      const TV br = DrF[fb + c * 64], bs = DsF[fb + c * 64], bt = DtF[fb + c * 64];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        yr[g] = M::mma(afr[g][c], br, yr[g]);
+        ys[g] = M::mma(afr[g][c], bs, ys[g]);
+        yt[g] = M::mma(afr[g][c], bt, yt[g]);
+      }
+      // keep at most a few chunks of operand loads in flight: hoisting all of
       // them costs enough registers to halve the occupancy
-      if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      if ((c & (4 / G - 1)) == 4 / G - 1) __builtin_amdgcn_sched_barrier(0);
     }
     const int q = 16 * t + dq;
-    double Q[4] = {0.0, 0.0, 0.0, 0.0};
-    if (q < TT::Nc) {
-      const int pm = q % TT::Nfq;
-      double adj[9], J;
-      pyr_metric(xv, ops.xg[pm % TT::n1], ops.xg[pm / TT::n1], adj, &J);
-      const double w = ops.wv[q];
-      double dr[4], ds[4], dtt[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        dr[v] = (double)yr[v];
-        ds[v] = (double)ys[v];
-        dtt[v] = (double)yt[v];
+    for (int g = 0; g < G; ++g) {
+      double Q[4] = {0.0, 0.0, 0.0, 0.0};
+      if (q < TT::Nc) {
+        const double* xv = sX[wv * EW + kEW * g + de];
+        const int pm = q % TT::Nfq;
+        double adj[9], J;
+        pyr_metric(xv, ops.xg[pm % TT::n1], ops.xg[pm / TT::n1], adj, &J);
+        const double w = ops.wv[q];
+        double dr[4], ds[4], dtt[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          dr[v] = (double)yr[g][v];
+          ds[v] = (double)ys[g][v];
+          dtt[v] = (double)yt[g][v];
+        }
+        double qp = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          qp += adj[k] * dr[1 + k] + adj[3 + k] * ds[1 + k] + adj[6 + k] * dtt[1 + k];
+        Q[0] = w * qp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          Q[1 + k] = w * (adj[k] * dr[0] + adj[3 + k] * ds[0] + adj[6 + k] * dtt[0]);
       }
-      double qp = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) qp += adj[k] * dr[1 + k] + adj[3 + k] * ds[1 + k] + adj[6 + k] * dtt[1 + k];
-      Q[0] = w * qp;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) Q[1 + k] = w * (adj[k] * dr[0] + adj[3 + k] * ds[0] + adj[6 + k] * dtt[0]);
+      for (int v = 0; v < 4; ++v) sQ[wv][g][M::row(de, v)][dq] = (TV)Q[v];
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sQ[wv][M::row(de, v)][dq] = (TV)Q[v];
-    __syncthreads();
+    wave_lds_sync();
     const size_t pb = (size_t)t * 4 * TT::NIT * 64;
 #pragma unroll
     for (int c2 = 0; c2 < 4; ++c2) {
-      const TV a = sQ[wv][row][4 * c2 + kq];
+      TV a[G];
 #pragma unroll
-      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, VF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+      for (int g = 0; g < G; ++g) a[g] = sQ[wv][g][row][4 * c2 + kq];
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) {
+        const TV b = VF[pb + (c2 * TT::NIT + u) * 64];
+#pragma unroll
+        for (int g = 0; g < G; ++g) z[g][u] = M::mma(a[g], b, z[g][u]);
+      }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
 
   // surface (Algorithm 2)
   for (int t = 0; t < TT::NTF; ++t) {
     const int q = 16 * t + dq;
-    double F[4] = {0.0, 0.0, 0.0, 0.0};
-    if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sQ[wv][M::row(de, v)][dq] = (TV)F[v];
-    __syncthreads();
+    for (int g = 0; g < G; ++g) {
+      const int64_t e = ew0 + kEW * g + de;
+      double F[4] = {0.0, 0.0, 0.0, 0.0};
+      if (e < mesh.K && q < TT::Nfc)
+        face_flux<TT::Nfq>(T, ops, mesh, sX[wv * EW + kEW * g + de], e, q, F);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sQ[wv][g][M::row(de, v)][dq] = (TV)F[v];
+    }
+    wave_lds_sync();
     const size_t pb = (size_t)t * 4 * TT::NIT * 64;
 #pragma unroll
     for (int c2 = 0; c2 < 4; ++c2) {
-      const TV a = sQ[wv][row][4 * c2 + kq];
+      TV a[G];
 #pragma unroll
-      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, LfF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+      for (int g = 0; g < G; ++g) a[g] = sQ[wv][g][row][4 * c2 + kq];
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) {
+        const TV b = LfF[pb + (c2 * TT::NIT + u) * 64];
+#pragma unroll
+        for (int g = 0; g < G; ++g) z[g][u] = M::mma(a[g], b, z[g][u]);
+      }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
 
   // inverse mass, material, RK stage (Algorithm 3)
-  if (e >= mesh.K) return;
-  const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
-  const double dte = dt * mesh.mat[e * 4 + 3];
 #pragma unroll
-  for (int u = 0; u < TT::NIT; ++u) {
-    const int i = 16 * u + dq;
-    if (i >= TT::Np) continue;
-    const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+  for (int g = 0; g < G; ++g) {
+    const int64_t e = ew0 + kEW * g + de;
+    if (e >= mesh.K) continue;
+    const double* xv = sX[wv * EW + kEW * g + de];
+    const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+    const double dte = dt * mesh.mat[e * 4 + 3];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double acc = (double)z[u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);
-      finish_coeff<MODE>(acc, minv, v == 0 ? kap : irho, out, R, (e * 4 + v) * TT::Np + i, ra,
-                         rb, dte);
+    for (int u = 0; u < TT::NIT; ++u) {
+      const int i = 16 * u + dq;
+      if (i >= TT::Np) continue;
+      const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double acc = (double)z[g][u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);
+        finish_coeff<MODE>(acc, minv, v == 0 ? kap : irho, out, R, (e * 4 + v) * TT::Np + i,
+                           ra, rb, dte);
+      }
     }
   }
 }
 
-template <int N, int FORM>
+// Element groups per wave for the fused stage and the trace (1 or 2).
+inline int mfma_groups(const dgpyr_ctx& c) { return c.mfma_groups == 2 ? 2 : 1; }
+
+template <int N, int FORM, int G>
 hipError_t stage_mfma_n(const dgpyr_ctx& c, int mode, const double* U, const double* T, double* out,
                         double* R, double ra, double rb, double dt, hipStream_t s) {
-  const int64_t nb = (c.K + kEB - 1) / kEB;
+  const int64_t nb = (c.K + kEB * G - 1) / (kEB * G);
   if (mode == 0)
-    hipLaunchKernelGGL((k_stage_mfma<N, FORM, 0>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T,
-                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+    hipLaunchKernelGGL((k_stage_mfma<N, FORM, 0, G>), dim3((unsigned)nb), dim3(kBlock), 0, s, U,
+                       T, c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
   else
-    hipLaunchKernelGGL((k_stage_mfma<N, FORM, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T,
-                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+    hipLaunchKernelGGL((k_stage_mfma<N, FORM, 1, G>), dim3((unsigned)nb), dim3(kBlock), 0, s, U,
+                       T, c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
   return hipGetLastError();
 }
 
@@ -364,15 +428,25 @@ template <int N>
 hipError_t stage_mfma_dispatch(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                                double* out, double* R, double ra, double rb, double dt,
                                hipStream_t s) {
-  if (c.precision == DGPYR_FP32_MFMA) return stage_mfma_n<N, 1>(c, mode, U, T, out, R, ra, rb, dt, s);
-  return stage_mfma_n<N, 0>(c, mode, U, T, out, R, ra, rb, dt, s);
+  const bool two = mfma_groups(c) == 2;
+  if (c.precision == DGPYR_FP32_MFMA)
+    return two ? stage_mfma_n<N, 1, 2>(c, mode, U, T, out, R, ra, rb, dt, s)
+               : stage_mfma_n<N, 1, 1>(c, mode, U, T, out, R, ra, rb, dt, s);
+  return two ? stage_mfma_n<N, 0, 2>(c, mode, U, T, out, R, ra, rb, dt, s)
+             : stage_mfma_n<N, 0, 1>(c, mode, U, T, out, R, ra, rb, dt, s);
+}
+
+template <int N, int G>
+hipError_t trace_mfma_g(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
+  const int64_t nb = (c.K + kEB * G - 1) / (kEB * G);
+  hipLaunchKernelGGL((k_trace_mfma<N, G>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T, c.frag,
+                     c.K);
+  return hipGetLastError();
 }
 
 template <int N>
 hipError_t trace_mfma_n(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
-  const int64_t nb = (c.K + kEB - 1) / kEB;
-  hipLaunchKernelGGL((k_trace_mfma<N>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T, c.frag, c.K);
-  return hipGetLastError();
+  return mfma_groups(c) == 2 ? trace_mfma_g<N, 2>(c, U, T, s) : trace_mfma_g<N, 1>(c, U, T, s);
 }
 
 template <int N, int FORM>

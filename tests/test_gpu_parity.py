@@ -27,6 +27,9 @@ PATHS = {"mfma": {}, "sumfact": {"sum_factorized": True}}
 # The sum-factorised kernels are disabled in the device build (setup returns
 # E_UNSUPPORTED); their parametrisations stay in the suite, skipped.
 PATH_PARAMS = [pytest.param("mfma"), pytest.param("sumfact", marks=HELD_BACK)]
+# 4-element groups per wave exercised per path (the fused matrix-core kernels
+# take 1 or 2; 0 = the library's default).
+GROUPS = {"mfma": (1, 2), "sumfact": (0,)}
 
 
 @pytest.mark.parametrize("path", PATH_PARAMS)
@@ -38,11 +41,12 @@ def test_rhs_parity_cfg1_all_orders(N, path):
     U = random_state(K, N, seed=100 + N)
     log(f"[parity] cfg1 N={N} K={K} path={path}")
     ref = AcousticDG(xyz, e2v, N, rho=rho, kappa=kap).rhs(U)
-    with _solver(xyz, e2v, N, rho=rho, kappa=kap, **PATHS[path]) as s:
-        got = gpu_rhs(s, U)
-    err = rel_err_per_field(got, ref)
-    log(f"[parity] cfg1 N={N} rel err per field {err}")
-    assert np.all(err < TOL), err
+    for g in GROUPS[path]:
+        with _solver(xyz, e2v, N, rho=rho, kappa=kap, groups_per_wave=g, **PATHS[path]) as s:
+            got = gpu_rhs(s, U)
+        err = rel_err_per_field(got, ref)
+        log(f"[parity] cfg1 N={N} groups={g} rel err per field {err}")
+        assert np.all(err < TOL), (g, err)
 
 
 @pytest.mark.parametrize("bc", ["wall", "free"])
@@ -84,9 +88,10 @@ def test_rhs_parity_ragged_subsets(nsub, path):
     U = random_state(nsub, N, seed=nsub)
     log(f"[parity] ragged K={nsub} path={path}")
     ref = AcousticDG(xyz, e2v, N).rhs(U)
-    with _solver(xyz, e2v, N, **PATHS[path]) as s:
-        got = gpu_rhs(s, U)
-    assert np.all(rel_err_per_field(got, ref) < TOL)
+    for g in GROUPS[path]:
+        with _solver(xyz, e2v, N, groups_per_wave=g, **PATHS[path]) as s:
+            got = gpu_rhs(s, U)
+        assert np.all(rel_err_per_field(got, ref) < TOL), g
 
 
 def test_rhs_parity_special_meshes():
@@ -110,12 +115,13 @@ def test_rhs_parity_eigenmode_data():
     assert np.all(rel_err_per_field(got, ref) < TOL)
 
 
-def test_rhs_bitwise_deterministic():
+@pytest.mark.parametrize("groups", [1, 2])
+def test_rhs_bitwise_deterministic(groups):
     import torch
     N = 4
     xyz, e2v = hex_pyramid_mesh(3, seed=6)
     U = random_state(e2v.shape[0], N, seed=2)
-    with _solver(xyz, e2v, N) as s:
+    with _solver(xyz, e2v, N, groups_per_wave=groups) as s:
         Ud = s.pack(torch.from_numpy(U).cuda())
         a = s.rhs(Ud).clone()
         b = s.rhs(Ud).clone()
@@ -134,14 +140,15 @@ def test_step_parity_lsrk(path):
     dt = 0.5 / (2.0 * (N + 1) * (N + 3) / 3.0 * o.inverse_length().max())
     nsteps = 10
     ref, _ = lsrk_run(o.rhs, U0, dt, nsteps)
-    with _solver(xyz, e2v, N, **PATHS[path]) as s:
-        U = s.pack(torch.from_numpy(U0).cuda())
-        R = s.empty_state().fill_(float("nan"))  # R is never read before it is written
-        s.step(U, R, dt, nsteps)
-        got = s.unpack(U).cpu().numpy()
-    err = rel_err_per_field(got, ref)
-    log(f"[parity] LSRK 10 steps rel err {err}")
-    assert np.all(err < 1e-11), err
+    for g in GROUPS[path]:
+        with _solver(xyz, e2v, N, groups_per_wave=g, **PATHS[path]) as s:
+            U = s.pack(torch.from_numpy(U0).cuda())
+            R = s.empty_state().fill_(float("nan"))  # R is never read before it is written
+            s.step(U, R, dt, nsteps)
+            got = s.unpack(U).cpu().numpy()
+        err = rel_err_per_field(got, ref)
+        log(f"[parity] LSRK 10 steps groups={g} rel err {err}")
+        assert np.all(err < 1e-11), (g, err)
 
 
 @pytest.mark.parametrize("path", PATH_PARAMS)
@@ -155,12 +162,13 @@ def test_rhs_parity_full_size_sampled(k1d, N, nsample, path):
     rng = np.random.default_rng(12)
     sample = np.unique(np.concatenate([rng.choice(K, nsample, replace=False), [0, K - 1]]))
     log(f"[parity] full-size K={K} N={N} sample={sample.size} path={path}")
-    with _solver(xyz, e2v, N, **PATHS[path]) as s:
-        got = gpu_rhs(s, U)
     ref = AcousticDG(xyz, e2v, N, elems=sample).rhs(U)
-    err = rel_err_per_field(got[sample], ref)
-    log(f"[parity] full-size rel err {err}")
-    assert np.all(err < TOL), err
+    for g in GROUPS[path]:
+        with _solver(xyz, e2v, N, groups_per_wave=g, **PATHS[path]) as s:
+            got = gpu_rhs(s, U)
+        err = rel_err_per_field(got[sample], ref)
+        log(f"[parity] full-size groups={g} rel err {err}")
+        assert np.all(err < TOL), (g, err)
 
 
 @pytest.mark.parametrize("N", [1, 4, 7])
@@ -184,12 +192,13 @@ def test_rhs_fp32_mfma_form(N):
     K = e2v.shape[0]
     U = random_state(K, N, seed=3)
     ref = AcousticDG(xyz, e2v, N).rhs(U)
-    with _solver(xyz, e2v, N, precision="fp32_mfma") as s:
-        got = gpu_rhs(s, U)
-    err = rel_err_per_field(got, ref)
-    log(f"[fp32] N={N} rel err per field {err}")
-    assert np.all(err < 2e-5), err
-    assert np.any(err > 1e-10), "FP32 form gave FP64-accurate results: wrong kernels?"
+    for g in (1, 2):
+        with _solver(xyz, e2v, N, precision="fp32_mfma", groups_per_wave=g) as s:
+            got = gpu_rhs(s, U)
+        err = rel_err_per_field(got, ref)
+        log(f"[fp32] N={N} groups={g} rel err per field {err}")
+        assert np.all(err < 2e-5), (g, err)
+        assert np.any(err > 1e-10), "FP32 form gave FP64-accurate results: wrong kernels?"
 
 
 @pytest.mark.parametrize("N", [2, 6])

@@ -146,6 +146,14 @@ def test_setup_errors_before_device(B):
     with pytest.raises(dg.DgpyrError) as ex:
         dg.Solver(xyz, e2v, 2, precision="split_bf16", alpha=-1.0)
     assert ex.value.status in (B.E_ARG, B.E_UNSUPPORTED)
+    # the sum-factorised kernels are not enabled in the device build
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Solver(xyz, e2v, 2, sum_factorized=True)
+    assert ex.value.status == B.E_UNSUPPORTED
+    # calls on a missing context fail without touching a device
+    L = B.lib()
+    assert L.dgpyr_set_groups(None, 1) != 0
+    assert L.dgpyr_set_groups(None, 3) != 0
 
 
 def test_nonconforming_triangle_apex(B):
