@@ -135,10 +135,12 @@ struct LaunchTimer {
 };
 
 // Default 4-element groups per wave of the fused matrix-core kernels.
+// Measured at 384000 pyramids, N = 4: two groups cut the FP64 stage from
+// 3.69 to 3.47 ms and the trace from 0.89 to 0.76 ms, but slow the FP32 stage
+// (2.84 -> 3.04 ms); for N >= 5 two FP64 groups no longer fit the registers
+// of two waves per SIMD.
 int default_groups(int N, int precision) {
-  (void)N;
-  (void)precision;
-  return 1;
+  return (precision == DGPYR_FP64 && N <= 4) ? 2 : 1;
 }
 
 // Kernel kinds per path, in dgpyr_step_timed order.
@@ -191,32 +193,44 @@ hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, doubl
   return e;
 }
 
-// Operator fragments in MFMA B order (layouts in context.hpp).
+// Operator fragments in MFMA B order, packed so that each lane reads KP =
+// 16 / sizeof(T) consecutive fragments with one 16-byte load (layouts in
+// context.hpp).  Entries outside the operator (and padding) are zero.
+template <typename T>
+constexpr int pack_of() { return (int)(16 / sizeof(T)); }
+
 template <typename T>
 std::vector<T> frag_rows(const std::vector<double>& Op, int P, int Np) {
-  // B[k][j] = Op[16t + j][4c + k], tiles t over P points, chunks c over Np
-  const int NT = (P + 15) / 16, NCH = (Np + 3) / 4;
-  std::vector<T> out((size_t)NT * NCH * 64, (T)0);
+  // B_c[k][j] = Op[16t + j][4c + k], tiles t over P points, chunks c over Np;
+  // stored [t][c / KP][lane][c % KP]
+  constexpr int KP = pack_of<T>();
+  const int NT = (P + 15) / 16, NCH = (Np + 3) / 4, NCHP = (NCH + KP - 1) / KP;
+  std::vector<T> out((size_t)NT * NCHP * 64 * KP, (T)0);
   for (int t = 0; t < NT; ++t)
     for (int c = 0; c < NCH; ++c)
       for (int l = 0; l < 64; ++l) {
         const int q = 16 * t + l % 16, n = 4 * c + l / 16;
-        if (q < P && n < Np) out[((size_t)t * NCH + c) * 64 + l] = (T)Op[(size_t)q * Np + n];
+        if (q < P && n < Np)
+          out[(((size_t)t * NCHP + c / KP) * 64 + l) * KP + c % KP] = (T)Op[(size_t)q * Np + n];
       }
   return out;
 }
 
 template <typename T>
 std::vector<T> frag_proj(const std::vector<double>& Op, int P, int Np) {
-  // B[k][j] = Op[16t + 4c + k][16u + j], tiles t over P points, u over Np
-  const int NT = (P + 15) / 16, NIT = (Np + 15) / 16;
-  std::vector<T> out((size_t)NT * 4 * NIT * 64, (T)0);
+  // B_u[k][j] = Op[16t + 4c + k][16u + j], tiles t over P points, c = 0..3,
+  // u over Np; stored [t][c][u / KP][lane][u % KP]
+  constexpr int KP = pack_of<T>();
+  const int NT = (P + 15) / 16, NIT = (Np + 15) / 16, NITP = (NIT + KP - 1) / KP;
+  std::vector<T> out((size_t)NT * 4 * NITP * 64 * KP, (T)0);
   for (int t = 0; t < NT; ++t)
     for (int c = 0; c < 4; ++c)
       for (int u = 0; u < NIT; ++u)
         for (int l = 0; l < 64; ++l) {
           const int q = 16 * t + 4 * c + l / 16, i = 16 * u + l % 16;
-          if (q < P && i < Np) out[(((size_t)t * 4 + c) * NIT + u) * 64 + l] = (T)Op[(size_t)q * Np + i];
+          if (q < P && i < Np)
+            out[((((size_t)t * 4 + c) * NITP + u / KP) * 64 + l) * KP + u % KP] =
+                (T)Op[(size_t)q * Np + i];
         }
   return out;
 }

@@ -34,12 +34,15 @@ struct DevOps {
 
 // Operators in MFMA B-fragment order (see mfma.hpp).  DrF, DsF, DtF, VF and
 // LfF are in the precision of the contraction form (double for FP64, float
-// for FP32_MFMA); the trace operator VfF is always double.
-//   DrF, DsF, DtF  [NTC][NCH][64]: D[16t + l%16][4c + l/16]       (derivatives)
-//   VF             [NTC][4][NIT][64]: V[16t + 4c + l/16][16u + l%16] (projection)
-//   VfF            [NTF][NCH][64]: Vf[16t + l%16][4c + l/16]      (trace)
-//   LfF            [NTF][4][NIT][64]: Vf[16t + 4c + l/16][16u + l%16] (lift)
-// Entries outside the operator are zero.
+// for FP32_MFMA); the trace operator VfF is always double.  Consecutive
+// fragments are interleaved by lane, KP = 16 / sizeof(element) at a time, so
+// that one 16-byte load per lane fetches KP fragments (lane l, slot j):
+//   DrF, DsF, DtF  [NTC][NCHP][64][KP]: D[16t + l%16][4(KP cp + j) + l/16]    (derivatives)
+//   VF             [NTC][4][NITP][64][KP]: V[16t + 4c + l/16][16(KP up + j) + l%16] (projection)
+//   VfF            [NTF][NCHP][64][2]: Vf[16t + l%16][4(2 cp + j) + l/16]     (trace)
+//   LfF            [NTF][4][NITP][64][KP]: Vf[16t + 4c + l/16][16(KP up + j) + l%16] (lift)
+// with NCHP = ceil(NCH / KP), NITP = ceil(NIT / KP).  Entries outside the
+// operator are zero.
 struct FragOps {
   const void* DrF;
   const void* DsF;

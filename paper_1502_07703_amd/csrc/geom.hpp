@@ -44,6 +44,38 @@ __host__ __device__ inline double pyr_jac(const double* x, double a, double b) {
   return J;
 }
 
+// J(a, b) is bilinear (Lemma 1): with B = P + a Q + b S + ab W and D = x4 - P,
+//   J = [B_a, B_b, (x4 - B)/2] = ([Q,S,D] + a [Q,W,D] + b [W,S,D] + ab [Q,S,W]) / 2,
+// [u,v,w] = (u x v).w (the (1+a)/2 B_a and (1+b)/2 B_b parts of x_t drop out of
+// the determinant, and the a^2, b^2 terms cancel).  c[4] = coefficients of
+// 1, a, b, ab.
+__host__ __device__ inline void pyr_jac_coeffs(const double* x, double* c) {
+  double P[3], Q[3], S[3], W[3], D[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double x0 = x[d], x1 = x[3 + d], x2 = x[6 + d], x3 = x[9 + d];
+    P[d] = 0.25 * (x0 + x1 + x2 + x3);
+    Q[d] = 0.25 * (-x0 + x1 + x2 - x3);
+    S[d] = 0.25 * (-x0 - x1 + x2 + x3);
+    W[d] = 0.25 * (x0 - x1 + x2 - x3);
+    D[d] = x[12 + d] - P[d];
+  }
+  const double qs0 = Q[1] * S[2] - Q[2] * S[1], qs1 = Q[2] * S[0] - Q[0] * S[2],
+               qs2 = Q[0] * S[1] - Q[1] * S[0];
+  const double qw0 = Q[1] * W[2] - Q[2] * W[1], qw1 = Q[2] * W[0] - Q[0] * W[2],
+               qw2 = Q[0] * W[1] - Q[1] * W[0];
+  const double ws0 = W[1] * S[2] - W[2] * S[1], ws1 = W[2] * S[0] - W[0] * S[2],
+               ws2 = W[0] * S[1] - W[1] * S[0];
+  c[0] = 0.5 * (qs0 * D[0] + qs1 * D[1] + qs2 * D[2]);
+  c[1] = 0.5 * (qw0 * D[0] + qw1 * D[1] + qw2 * D[2]);
+  c[2] = 0.5 * (ws0 * D[0] + ws1 * D[1] + ws2 * D[2]);
+  c[3] = 0.5 * (qs0 * W[0] + qs1 * W[1] + qs2 * W[2]);
+}
+
+__host__ __device__ inline double pyr_jac_eval(const double* c, double a, double b) {
+  return c[0] + a * c[1] + b * (c[2] + a * c[3]);
+}
+
 // Outward area-weighted normal N (|N| = surface Jacobian of the face
 // parametrisation) on face f at collapsed (a, b):
 //   base (c = -1):      N = -B_a x B_b                      (varies with a, b)

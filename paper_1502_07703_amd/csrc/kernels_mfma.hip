@@ -69,10 +69,13 @@ __global__ __launch_bounds__(kBlock) void k_volume_mfma(const double* __restrict
   load_u_frags<N, FORM>(U, ew0, mesh.K, lane, afr);
   __syncthreads();
 
-  const T* DrF = static_cast<const T*>(fo.DrF) + lane;
-  const T* DsF = static_cast<const T*>(fo.DsF) + lane;
-  const T* DtF = static_cast<const T*>(fo.DtF) + lane;
-  const T* VF = static_cast<const T*>(fo.VF) + lane;
+  constexpr int KP = Pack<T>::KP;
+  constexpr int NCHP = (TT::NCH + KP - 1) / KP, NITP = (TT::NIT + KP - 1) / KP;
+  using PV = typename Pack<T>::V;
+  const T* DrF = static_cast<const T*>(fo.DrF) + lane * KP;
+  const T* DsF = static_cast<const T*>(fo.DsF) + lane * KP;
+  const T* DtF = static_cast<const T*>(fo.DtF) + lane * KP;
+  const T* VF = static_cast<const T*>(fo.VF) + lane * KP;
   const int de = lane >> 4, dq = lane & 15;
   const int row = lane & 15, kq = lane >> 4;
   const double* xv = sX[wv * kEW + de];
@@ -82,12 +85,19 @@ __global__ __launch_bounds__(kBlock) void k_volume_mfma(const double* __restrict
 
   for (int t = 0; t < TT::NTC; ++t) {
     typename M::Acc yr = M::zero(), ys = M::zero(), yt = M::zero();
-    const size_t fb = (size_t)t * TT::NCH * 64;
+    const size_t fb = (size_t)t * NCHP * 64 * KP;
+    PV pr, ps, pt;
 #pragma unroll
     for (int c = 0; c < TT::NCH; ++c) {
-      yr = M::mma(afr[c], DrF[fb + c * 64], yr);
-      ys = M::mma(afr[c], DsF[fb + c * 64], ys);
-      yt = M::mma(afr[c], DtF[fb + c * 64], yt);
+      if (c % KP == 0) {
+        const size_t o = fb + (size_t)(c / KP) * 64 * KP;
+        pr = load_pack(DrF + o);
+        ps = load_pack(DsF + o);
+        pt = load_pack(DtF + o);
+      }
+      yr = M::mma(afr[c], pr[c % KP], yr);
+      ys = M::mma(afr[c], ps[c % KP], ys);
+      yt = M::mma(afr[c], pt[c % KP], yt);
       // keep at most four chunks of operand loads in flight: hoisting all of
       // them costs enough registers to halve the occupancy
       if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -118,12 +128,16 @@ __global__ __launch_bounds__(kBlock) void k_volume_mfma(const double* __restrict
     sQ[wv][M::row(de, 2)][dq] = (T)Q2;
     sQ[wv][M::row(de, 3)][dq] = (T)Q3;
     __syncthreads();
-    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+    const size_t pb = (size_t)t * 4 * NITP * 64 * KP;
 #pragma unroll
     for (int c2 = 0; c2 < 4; ++c2) {
       const T a = sQ[wv][row][4 * c2 + kq];
+      PV pv;
 #pragma unroll
-      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, VF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+      for (int u = 0; u < TT::NIT; ++u) {
+        if (u % KP == 0) pv = load_pack(VF + pb + ((size_t)c2 * NITP + u / KP) * 64 * KP);
+        z[u] = M::mma(a, pv[u % KP], z[u]);
+      }
     }
     __syncthreads();
   }
@@ -157,18 +171,21 @@ __global__ __launch_bounds__(kBlock) void k_trace_mfma(const double* __restrict_
   double afr[G][TT::NCH];
 #pragma unroll
   for (int g = 0; g < G; ++g) load_u_frags<N, 0>(U, ew0 + kEW * g, K, lane, afr[g]);
-  const double* VfF = static_cast<const double*>(fo.VfF) + lane;
+  constexpr int KP = Pack<double>::KP;
+  constexpr int NCHP = (TT::NCH + KP - 1) / KP;
+  const double* VfF = static_cast<const double*>(fo.VfF) + lane * KP;
   const int de = lane >> 4, dq = lane & 15;
   for (int t = 0; t < TT::NTF; ++t) {
     M::Acc y[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) y[g] = M::zero();
-    const size_t fb = (size_t)t * TT::NCH * 64;
+    const size_t fb = (size_t)t * NCHP * 64 * KP;
+    dx2 pk;
 #pragma unroll
     for (int c = 0; c < TT::NCH; ++c) {
-      const double b = VfF[fb + c * 64];
+      if (c % KP == 0) pk = load_pack(VfF + fb + (size_t)(c / KP) * 64 * KP);
 #pragma unroll
-      for (int g = 0; g < G; ++g) y[g] = M::mma(afr[g][c], b, y[g]);
+      for (int g = 0; g < G; ++g) y[g] = M::mma(afr[g][c], pk[c % KP], y[g]);
     }
     const int q = 16 * t + dq;
 #pragma unroll
@@ -207,7 +224,10 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
   const int row = lane & 15, kq = lane >> 4;
   const int64_t e = ew0 + de;
   const double* xv = sX[wv * kEW + de];
-  const TV* LfF = static_cast<const TV*>(fo.LfF) + lane;
+  constexpr int KP = Pack<TV>::KP;
+  constexpr int NITP = (TT::NIT + KP - 1) / KP;
+  using PV = typename Pack<TV>::V;
+  const TV* LfF = static_cast<const TV*>(fo.LfF) + lane * KP;
   typename M::Acc z[TT::NIT];
 #pragma unroll
   for (int u = 0; u < TT::NIT; ++u) z[u] = M::zero();
@@ -218,12 +238,16 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 #pragma unroll
     for (int v = 0; v < 4; ++v) sF[wv][M::row(de, v)][dq] = (TV)F[v];
     __syncthreads();
-    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+    const size_t pb = (size_t)t * 4 * NITP * 64 * KP;
 #pragma unroll
     for (int c2 = 0; c2 < 4; ++c2) {
       const TV a = sF[wv][row][4 * c2 + kq];
+      PV pv;
 #pragma unroll
-      for (int u = 0; u < TT::NIT; ++u) z[u] = M::mma(a, LfF[pb + (c2 * TT::NIT + u) * 64], z[u]);
+      for (int u = 0; u < TT::NIT; ++u) {
+        if (u % KP == 0) pv = load_pack(LfF + pb + ((size_t)c2 * NITP + u / KP) * 64 * KP);
+        z[u] = M::mma(a, pv[u % KP], z[u]);
+      }
     }
     __syncthreads();
   }
@@ -278,11 +302,14 @@ __global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restri
   for (int g = 0; g < G; ++g) load_u_frags<N, FORM>(U, ew0 + kEW * g, mesh.K, lane, afr[g]);
   __syncthreads();
 
-  const TV* DrF = static_cast<const TV*>(fo.DrF) + lane;
-  const TV* DsF = static_cast<const TV*>(fo.DsF) + lane;
-  const TV* DtF = static_cast<const TV*>(fo.DtF) + lane;
-  const TV* VF = static_cast<const TV*>(fo.VF) + lane;
-  const TV* LfF = static_cast<const TV*>(fo.LfF) + lane;
+  constexpr int KP = Pack<TV>::KP;
+  constexpr int NCHP = (TT::NCH + KP - 1) / KP, NITP = (TT::NIT + KP - 1) / KP;
+  using PV = typename Pack<TV>::V;
+  const TV* DrF = static_cast<const TV*>(fo.DrF) + lane * KP;
+  const TV* DsF = static_cast<const TV*>(fo.DsF) + lane * KP;
+  const TV* DtF = static_cast<const TV*>(fo.DtF) + lane * KP;
+  const TV* VF = static_cast<const TV*>(fo.VF) + lane * KP;
+  const TV* LfF = static_cast<const TV*>(fo.LfF) + lane * KP;
   const int de = lane >> 4, dq = lane & 15;
   const int row = lane & 15, kq = lane >> 4;
   typename M::Acc z[G][TT::NIT];
@@ -296,15 +323,21 @@ __global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restri
     typename M::Acc yr[G], ys[G], yt[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) yr[g] = ys[g] = yt[g] = M::zero();
-    const size_t fb = (size_t)t * TT::NCH * 64;
+    const size_t fb = (size_t)t * NCHP * 64 * KP;
+    PV pr, ps, pt;
 #pragma unroll
     for (int c = 0; c < TT::NCH; ++c) {
-      const TV br = DrF[fb + c * 64], bs = DsF[fb + c * 64], bt = DtF[fb + c * 64];
+      if (c % KP == 0) {
+        const size_t o = fb + (size_t)(c / KP) * 64 * KP;
+        pr = load_pack(DrF + o);
+        ps = load_pack(DsF + o);
+        pt = load_pack(DtF + o);
+      }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        yr[g] = M::mma(afr[g][c], br, yr[g]);
-        ys[g] = M::mma(afr[g][c], bs, ys[g]);
-        yt[g] = M::mma(afr[g][c], bt, yt[g]);
+        yr[g] = M::mma(afr[g][c], pr[c % KP], yr[g]);
+        ys[g] = M::mma(afr[g][c], ps[c % KP], ys[g]);
+        yt[g] = M::mma(afr[g][c], pt[c % KP], yt[g]);
       }
       // keep at most a few chunks of operand loads in flight: hoisting all of
       // them costs enough registers to halve the occupancy
@@ -340,17 +373,18 @@ __global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restri
       for (int v = 0; v < 4; ++v) sQ[wv][g][M::row(de, v)][dq] = (TV)Q[v];
     }
     wave_lds_sync();
-    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+    const size_t pb = (size_t)t * 4 * NITP * 64 * KP;
 #pragma unroll
     for (int c2 = 0; c2 < 4; ++c2) {
       TV a[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) a[g] = sQ[wv][g][row][4 * c2 + kq];
+      PV pv;
 #pragma unroll
       for (int u = 0; u < TT::NIT; ++u) {
-        const TV b = VF[pb + (c2 * TT::NIT + u) * 64];
+        if (u % KP == 0) pv = load_pack(VF + pb + ((size_t)c2 * NITP + u / KP) * 64 * KP);
 #pragma unroll
-        for (int g = 0; g < G; ++g) z[g][u] = M::mma(a[g], b, z[g][u]);
+        for (int g = 0; g < G; ++g) z[g][u] = M::mma(a[g], pv[u % KP], z[g][u]);
       }
     }
     wave_lds_sync();
@@ -369,17 +403,18 @@ __global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restri
       for (int v = 0; v < 4; ++v) sQ[wv][g][M::row(de, v)][dq] = (TV)F[v];
     }
     wave_lds_sync();
-    const size_t pb = (size_t)t * 4 * TT::NIT * 64;
+    const size_t pb = (size_t)t * 4 * NITP * 64 * KP;
 #pragma unroll
     for (int c2 = 0; c2 < 4; ++c2) {
       TV a[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) a[g] = sQ[wv][g][row][4 * c2 + kq];
+      PV pv;
 #pragma unroll
       for (int u = 0; u < TT::NIT; ++u) {
-        const TV b = LfF[pb + (c2 * TT::NIT + u) * 64];
+        if (u % KP == 0) pv = load_pack(LfF + pb + ((size_t)c2 * NITP + u / KP) * 64 * KP);
 #pragma unroll
-        for (int g = 0; g < G; ++g) z[g][u] = M::mma(a[g], b, z[g][u]);
+        for (int g = 0; g < G; ++g) z[g][u] = M::mma(a[g], pv[u % KP], z[g][u]);
       }
     }
     wave_lds_sync();
@@ -390,14 +425,15 @@ __global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restri
   for (int g = 0; g < G; ++g) {
     const int64_t e = ew0 + kEW * g + de;
     if (e >= mesh.K) continue;
-    const double* xv = sX[wv * EW + kEW * g + de];
+    double jc[4];
+    pyr_jac_coeffs(sX[wv * EW + kEW * g + de], jc);
     const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
     const double dte = dt * mesh.mat[e * 4 + 3];
 #pragma unroll
     for (int u = 0; u < TT::NIT; ++u) {
       const int i = 16 * u + dq;
       if (i >= TT::Np) continue;
-      const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+      const double minv = 1.0 / (pyr_jac_eval(jc, ops.na[i], ops.nb[i]) * ops.wwc[i]);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double acc = (double)z[g][u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);

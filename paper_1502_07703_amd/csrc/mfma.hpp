@@ -13,9 +13,11 @@
 // cases lane l ends owning all four fields (register v = field) of element
 // l / 16 at column l % 16 -- what the pointwise geometry and flux work needs:
 // FP32 rows are i = 4 e + f, FP64 rows are i = 4 f + e.
-// Operators are stored on the device in "fragment order": the 64 values of
-// one B operand are contiguous, so each operand load is one coalesced
-// 512-byte (FP64) or 256-byte (FP32) read.
+// Operators are stored on the device in "fragment order", consecutive B
+// operands interleaved by lane 16 bytes at a time (2 FP64 or 4 FP32
+// fragments), so that one coalesced 16-byte-per-lane load fetches several
+// operands: the vector-memory address unit, not bandwidth, limits a kernel
+// that issues one narrow load per matrix-core product.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,6 +26,27 @@ namespace dgpyr {
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// 16-byte packs of operator fragments: KP fragments per lane per load.
+typedef double dx2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Pack;
+template <>
+struct Pack<double> {
+  using V = dx2;
+  static constexpr int KP = 2;
+};
+template <>
+struct Pack<float> {
+  using V = fx4;
+  static constexpr int KP = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Pack<T>::V load_pack(const T* p) {
+  return *reinterpret_cast<const typename Pack<T>::V*>(p);
+}
 
 // Precision forms of the contractions.  FORM 0: FP64 operands, FP64
 // accumulation.  FORM 1: FP32 operands, FP32 accumulation.
