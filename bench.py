@@ -168,6 +168,113 @@ def timed_steps(dg, solver, U, R, t0, dt, nsteps, stream):
     return time.perf_counter() - w0, names, list(ms), list(cnt)
 
 
+def precision_study(args):
+    """FP64 vs FP32-MFMA vs split-BF16 on one mesh for several N and modes m:
+    throughput of each form and its L2 error against the exact mode and
+    against the FP64 result after the same steps (equal error: within 10 % of
+    the FP64 error).  Prints one JSON line per (N, m) and a summary line."""
+    import torch
+
+    import paper_1502_07703_amd as dg
+    from synth import hex_pyramid_mesh
+    xyz, e2v = hex_pyramid_mesh(args.study_k1d, seed=3)
+    K = e2v.shape[0]
+    stream = torch.cuda.current_stream()
+    rows = []
+    for N in [int(x) for x in args.study_N.split(",")]:
+        Np = n_basis(N)
+        for m in [int(x) for x in args.study_modes.split(",")]:
+            res = {"N": N, "m": m, "nelems": K, "steps": args.study_steps}
+            ref_state = None
+            for form in ("fp64", "fp32_mfma", "split_bf16"):
+                print(f"[study] N={N} m={m} {form}", file=sys.stderr, flush=True)
+                with dg.Solver(xyz, e2v, N, precision=form) as s:
+                    P, wJ = s.volume_points()
+                    U = s.project(wall_mode_values(P, m, 0.0))
+                    R = s.empty_state().zero_()
+                    dt = s.stable_dt(0.5)
+                    wall, names, ms, cnt = timed_steps(dg, s, U, R, 0.0, dt, args.study_steps,
+                                                       stream)
+                    T_end = args.study_steps * dt
+                    e = l2_norm(s, U, P, wJ, wall_mode_values(P, m, T_end))
+                    entry = {"gdof_stages_per_s": 4 * Np * K * 5 * args.study_steps / wall / 1e9,
+                             "l2_error_vs_mode": e,
+                             "kernels_ms": {nm: ms[i] / max(cnt[i], 1) for i, nm in enumerate(names)}}
+                    if form == "fp64":
+                        ref_state = U.clone()
+                        res["t"] = T_end
+                    else:
+                        entry["l2_diff_vs_fp64"] = l2_norm(s, U - ref_state, P, wJ)
+                    del P, wJ
+                res[form] = entry
+                torch.cuda.empty_cache()
+            e64 = res["fp64"]["l2_error_vs_mode"]
+            for form in ("fp32_mfma", "split_bf16"):
+                f = res[form]
+                f["speedup_vs_fp64"] = f["gdof_stages_per_s"] / res["fp64"]["gdof_stages_per_s"]
+                f["equal_error"] = abs(f["l2_error_vs_mode"] - e64) <= 0.1 * e64
+            print(json.dumps({"study": "precision_forms", **res}), flush=True)
+            rows.append(res)
+            del ref_state
+            torch.cuda.empty_cache()
+    return rows
+
+
+def batch_bench(args):
+    """Batched form: independent problems of uneven size (K1D ~ U{lo..hi}
+    hexes per side, x 6 pyramids) and order (N ~ U{2..6}), per-element c^2 ~
+    U[0.5, 2], one Ricker point source (f0 = 10) at a random location each;
+    all advanced together (per-problem CFL time steps) through one captured
+    step graph.  Prints one JSON line."""
+    import torch
+
+    import paper_1502_07703_amd as dg
+    from synth import hex_pyramid_mesh
+    rng = np.random.default_rng(4000)
+    lo, hi = [int(x) for x in args.batch_k1d.split(",")]
+    probs = []
+    for i in range(args.batch_problems):
+        k1d = int(rng.integers(lo, hi + 1))
+        N = int(rng.integers(2, 7))
+        xyz, e2v = hex_pyramid_mesh(k1d, seed=4000 + i)
+        K = e2v.shape[0]
+        kap = rng.uniform(0.5, 2.0, K)
+        src = [dict(x=list(rng.uniform(0.1, 0.9, 3)), f0=10.0)]
+        probs.append(dict(xyz=xyz, e2v=e2v, N=N, rho=np.ones(K), kappa=kap, sources=src))
+    t_setup = time.perf_counter()
+    b = dg.Batch(probs, cfl=0.5)
+    t_setup = time.perf_counter() - t_setup
+    print(f"[batch] setup {t_setup:.1f} s, {len(probs)} problems, {b.ngroups} groups",
+          file=sys.stderr, flush=True)
+    U = b.empty_state().zero_()
+    R = b.empty_state().zero_()
+    stream = torch.cuda.current_stream()
+    chosen = b.tune(2)
+    b.step(U, R, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(U, R, args.steps, step0=args.warmup)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if not torch.isfinite(U).all():
+        print("non-finite batch state", file=sys.stderr)
+        sys.exit(1)
+    dof = sum(4 * sl["Np"] * sl["nelems"] for sl in b.slots)
+    nel = sum(sl["nelems"] for sl in b.slots)
+    out = {"metric": "GDOF·stages/s, batched independent problems", "value":
+           dof * 5 * args.steps / wall / 1e9, "unit": "GDOF·stages/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{len(probs)} independent problems, K1D ~ U{{{lo}..{hi}}} x 6 "
+                                  "pyramids, N ~ U{2..6}, c^2 ~ U[0.5,2] per element, one Ricker "
+                                  "source each, per-problem CFL 0.5 time steps",
+                      "problems": len(probs), "nelems": nel, "dof": dof, "groups": b.ngroups,
+                      "tuned_groups_per_wave": chosen, "setup_s": t_setup}}
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +300,16 @@ def main():
                     help="skip the FP32-MFMA / split-BF16 comparison on the same workload")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched independent problems instead of the bench line")
+    ap.add_argument("--batch-problems", type=int, default=256)
+    ap.add_argument("--batch-k1d", default="4,24")
+    ap.add_argument("--study", action="store_true",
+                    help="precision-form study instead of the bench line (see --study-*)")
+    ap.add_argument("--study-k1d", type=int, default=64)
+    ap.add_argument("--study-N", default="5,6,7")
+    ap.add_argument("--study-modes", default="1,8")
+    ap.add_argument("--study-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
@@ -207,6 +324,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.study:
+        precision_study(args)
+        return
+    if args.batch:
+        batch_bench(args)
+        return
     N = args.N
     Np = n_basis(N)
     xyz, e2v = hex_pyramid_mesh(args.k1d, seed=2)

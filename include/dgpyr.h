@@ -164,14 +164,74 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* ctx, double* U, double* R, double t0, d
  * order used by dgpyr_step_timed; the string lives as long as the context. */
 const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
 
-/* Work shape of the fused matrix-core kernels (FP64 and FP32 forms, and
- * their trace kernel): groups_per_wave = number of 4-element groups one wave
- * owns, so that each operator fragment loaded feeds that many matrix-core
- * products.  1 or 2; 0 restores the library's choice for the context's N.
+/* Work shape of the fused matrix-core stage kernel (FP64 and FP32 forms):
+ * groups_per_wave = number of 4-element groups one wave owns, so that each
+ * operator fragment loaded feeds that many matrix-core products (the trace
+ * kernel's shape is chosen by the library).  1 or 2; 0 restores the
+ * library's choice for the context's N.
  * Results are identical up to the same rounding for every choice.  Takes
  * effect at the next launch; not synchronised with work already queued.
  * Errors: E_ARG for other values. */
 dgpyr_status dgpyr_set_groups(dgpyr_ctx* ctx, int32_t groups_per_wave);
+
+/* ---- Batches of independent problems (uneven sizes and orders) ----------
+ * Problems are grouped by (N, bc); a group's meshes are concatenated into one
+ * context whose elements carry their problem's time step.  The state of the
+ * batch is one device array: problem i occupies [offset, offset + len) in the
+ * canonical layout [nelems][4][Np] of its order.  Every call returns a status
+ * and never aborts. */
+typedef struct dgpyr_batch dgpyr_batch;
+
+typedef struct {
+  int32_t group;          /* group index (problems sharing N and bc)             */
+  int32_t N;              /* order                                               */
+  int32_t Np;             /* basis functions per element                         */
+  int32_t reserved;       /* 0                                                   */
+  int64_t nelems;         /* elements of the problem                             */
+  int64_t elem_offset;    /* first element inside its group                      */
+  int64_t offset;         /* first double of the problem in the batch state      */
+  int64_t len;            /* doubles of the problem (nelems * 4 * Np)            */
+  double dt;              /* the problem's time step                             */
+  double inv_length_max;  /* max over its elements of c_K |dK| / |K|             */
+} dgpyr_batch_slot;
+
+/* nproblems meshes (host arrays, each with its own bc, materials and point
+ * sources), orders[i] in [0, DGPYR_MAX_ORDER], one dgpyr_opts for all.  Time
+ * step of problem i: dts[i] if dts is non-NULL, else the CFL rule of Section
+ * 4.3, cfl / (2(N+1)(N+3)/3 * max_K c_K |dK|/|K|) over its own elements.
+ * Synchronous.  Errors as dgpyr_setup, for the first failing group. */
+dgpyr_status dgpyr_batch_setup(const dgpyr_mesh* meshes, const int32_t* orders,
+                               const double* dts, double cfl, int32_t nproblems,
+                               const dgpyr_opts* opts, dgpyr_batch** out);
+
+/* Total doubles of the batch state and the number of groups. */
+dgpyr_status dgpyr_batch_info(const dgpyr_batch* b, int64_t* state_len, int32_t* ngroups);
+
+/* Layout and time step of problem i. */
+dgpyr_status dgpyr_batch_problem(const dgpyr_batch* b, int32_t i, dgpyr_batch_slot* slot);
+
+/* The context of group g (for dgpyr_volume_points / project / eval on that
+ * group's part of the state, which starts at *state_offset).  Owned by the
+ * batch; do not destroy. */
+dgpyr_status dgpyr_batch_group(dgpyr_batch* b, int32_t g, dgpyr_ctx** ctx, int64_t* state_offset);
+
+/* nsteps LSRK(5,4) steps of every problem, each with its own time step;
+ * step0 is the number of steps already taken (source times are
+ * (step0 + n + c_s) dt_i).  One step of all groups is captured once into a
+ * HIP graph (re-captured when U or R change) and replayed nsteps times on the
+ * stream.  U, R: device arrays of the batch state length.  Asynchronous. */
+dgpyr_status dgpyr_batch_step(dgpyr_batch* b, double* U, double* R, int64_t step0, int32_t nsteps,
+                              void* stream);
+
+/* Autotuner: for every group on a matrix-core FP64/FP32 path, times nsteps
+ * steps on scratch state for 1 and 2 element groups per wave and keeps the
+ * faster (chosen[g] receives it, 0 for groups with nothing to tune; chosen
+ * may be NULL).  Allocates and frees scratch device memory; synchronises the
+ * stream. */
+dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, int32_t nsteps, void* stream, int32_t* chosen);
+
+/* Releases the batch, its contexts and graph. */
+void dgpyr_batch_destroy(dgpyr_batch* b);
 
 /* Host-only inspection of the reference data the library builds for degree N
  * (no device needed).  which: 0 volume weights [Nc]; 1 V [Nc][Np];

@@ -15,7 +15,7 @@ import numpy as np
 from . import _binding as B
 from ._binding import DgpyrError
 
-__all__ = ["Solver", "DgpyrError", "n_basis", "LSRK_CFL_CONSTANT"]
+__all__ = ["Solver", "Batch", "DgpyrError", "n_basis", "LSRK_CFL_CONSTANT"]
 
 
 def n_basis(N: int) -> int:
@@ -44,36 +44,66 @@ def _dptr(t, length=None, name="array"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _sources_array(sources):
+    """Point sources as an (n, 6) float64 array: x, y, z, amplitude, f0, delay.
+    Accepts such an array or a list of dicts with keys x (3), f0, and optional
+    amp (1) and t0 (delay; <= 0 or missing means 1/f0)."""
+    if sources is None or len(sources) == 0:
+        return None
+    if isinstance(sources, np.ndarray):
+        a = np.ascontiguousarray(sources, dtype=np.float64)
+    else:
+        a = np.array([[*s["x"], s.get("amp", 1.0), s["f0"], s.get("t0") or 0.0] for s in sources],
+                     dtype=np.float64)
+    if a.ndim != 2 or a.shape[1] != 6:
+        raise ValueError("sources must have shape (n, 6)")
+    return a
+
+
+class _HostMesh:
+    """Host arrays of one mesh kept alive while the library reads them."""
+
+    def __init__(self, xyz, e2v, rho=None, kappa=None, bc="wall", sources=None):
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.e2v = np.ascontiguousarray(e2v, dtype=np.int64)
+        if self.xyz.ndim != 2 or self.xyz.shape[1] != 3:
+            raise ValueError("xyz must have shape (nverts, 3)")
+        if self.e2v.ndim != 2 or self.e2v.shape[1] != 5:
+            raise ValueError("e2v must have shape (nelems, 5)")
+        K = self.e2v.shape[0]
+        self.rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        self.kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+        for a, nm in ((self.rho, "rho"), (self.kappa, "kappa")):
+            if a is not None and a.shape != (K,):
+                raise ValueError(f"{nm} must have shape ({K},)")
+        self.src = _sources_array(sources)
+        dptr = ctypes.POINTER(ctypes.c_double)
+        self.struct = B.Mesh(
+            nverts=self.xyz.shape[0], xyz=self.xyz.ctypes.data_as(dptr),
+            nelems=K, e2v=self.e2v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            rho=None if self.rho is None else self.rho.ctypes.data_as(dptr),
+            kappa=None if self.kappa is None else self.kappa.ctypes.data_as(dptr),
+            bc=B.BC[bc], nsources=0 if self.src is None else self.src.shape[0],
+            sources=None if self.src is None else self.src.ctypes.data_as(dptr))
+
+
+def _opts(precision, alpha, reference_kernels=False, unfused=False, sum_factorized=False):
+    flags = (B.FLAG_REFERENCE_KERNELS if reference_kernels else 0) | \
+        (B.FLAG_UNFUSED if unfused else 0) | \
+        (B.FLAG_SUM_FACTORIZED if sum_factorized else 0)
+    return B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=flags)
+
+
 class Solver:
     """A mesh and a discretisation set up on the current HIP device."""
 
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
                  precision="fp64", reference_kernels=False, unfused=False,
-                 sum_factorized=False, groups_per_wave=0, stream=None):
+                 sum_factorized=False, groups_per_wave=0, sources=None, stream=None):
         L = B.lib()
-        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
-        self._e2v = np.ascontiguousarray(e2v, dtype=np.int64)
-        if self._xyz.ndim != 2 or self._xyz.shape[1] != 3:
-            raise ValueError("xyz must have shape (nverts, 3)")
-        if self._e2v.ndim != 2 or self._e2v.shape[1] != 5:
-            raise ValueError("e2v must have shape (nelems, 5)")
-        K = self._e2v.shape[0]
-        self._rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
-        self._kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
-        for a, nm in ((self._rho, "rho"), (self._kappa, "kappa")):
-            if a is not None and a.shape != (K,):
-                raise ValueError(f"{nm} must have shape ({K},)")
-        dptr = ctypes.POINTER(ctypes.c_double)
-        mesh = B.Mesh(
-            nverts=self._xyz.shape[0], xyz=self._xyz.ctypes.data_as(dptr),
-            nelems=K, e2v=self._e2v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-            rho=None if self._rho is None else self._rho.ctypes.data_as(dptr),
-            kappa=None if self._kappa is None else self._kappa.ctypes.data_as(dptr),
-            bc=B.BC[bc])
-        flags = (B.FLAG_REFERENCE_KERNELS if reference_kernels else 0) | \
-            (B.FLAG_UNFUSED if unfused else 0) | \
-            (B.FLAG_SUM_FACTORIZED if sum_factorized else 0)
-        opts = B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=flags)
+        self._host = _HostMesh(xyz, e2v, rho, kappa, bc, sources)
+        mesh = self._host.struct
+        opts = _opts(precision, alpha, reference_kernels, unfused, sum_factorized)
         handle = ctypes.c_void_p()
         st = L.dgpyr_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
                            _stream_handle(stream) if stream is not None else None,
@@ -170,6 +200,106 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             B.lib().dgpyr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class _GroupView(Solver):
+    """Solver methods on one group context of a batch (not owned)."""
+
+    def __init__(self, handle):  # noqa: D107  (no mesh: the batch built it)
+        L = B.lib()
+        self._h = handle
+        info = B.Info()
+        B.check(L.dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
+        self.info = {k: getattr(info, k) for k, _ in B.Info._fields_}
+        self.N, self.Np, self.K = info.N, info.Np, info.nelems
+        self.state_len, self.canon_len = info.state_len, info.canon_len
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """Independent problems of uneven sizes and orders advanced together.
+
+    ``problems``: list of dicts with keys ``xyz``, ``e2v``, ``N`` and optional
+    ``rho``, ``kappa``, ``bc``, ``sources``.  Each problem has its own time
+    step (``dts`` or the CFL rule).  The batch state is one device array;
+    ``view(U, i)`` is problem i's (nelems, 4, Np) part.
+    """
+
+    def __init__(self, problems, precision="fp64", alpha=1.0, dts=None, cfl=0.5):
+        L = B.lib()
+        self._hosts = [_HostMesh(p["xyz"], p["e2v"], p.get("rho"), p.get("kappa"),
+                                 p.get("bc", "wall"), p.get("sources")) for p in problems]
+        n = len(problems)
+        meshes = (B.Mesh * n)(*[h.struct for h in self._hosts])
+        orders = (ctypes.c_int32 * n)(*[int(p["N"]) for p in problems])
+        dts_arr = None if dts is None else (ctypes.c_double * n)(*[float(x) for x in dts])
+        opts = _opts(precision, alpha)
+        h = ctypes.c_void_p()
+        B.check(L.dgpyr_batch_setup(meshes, orders, dts_arr, float(cfl), n, ctypes.byref(opts),
+                                    ctypes.byref(h)), "dgpyr_batch_setup")
+        self._h = h
+        sl, ng = ctypes.c_int64(), ctypes.c_int32()
+        B.check(L.dgpyr_batch_info(h, ctypes.byref(sl), ctypes.byref(ng)), "dgpyr_batch_info")
+        self.state_len, self.ngroups = sl.value, ng.value
+        self.slots = []
+        for i in range(n):
+            s = B.BatchSlot()
+            B.check(L.dgpyr_batch_problem(h, i, ctypes.byref(s)), "dgpyr_batch_problem")
+            self.slots.append({k: getattr(s, k) for k, _ in B.BatchSlot._fields_ if k != "reserved"})
+        self.groups = []
+        for g in range(self.ngroups):
+            c, off = ctypes.c_void_p(), ctypes.c_int64()
+            B.check(L.dgpyr_batch_group(h, g, ctypes.byref(c), ctypes.byref(off)),
+                    "dgpyr_batch_group")
+            self.groups.append((_GroupView(c), off.value))
+
+    def empty_state(self):
+        import torch
+        return torch.empty(self.state_len, dtype=torch.float64, device="cuda")
+
+    def view(self, U, i):
+        """Problem i's part of a batch state array, shape (nelems, 4, Np)."""
+        s = self.slots[i]
+        return U[s["offset"]:s["offset"] + s["len"]].view(s["nelems"], 4, s["Np"])
+
+    def group_state(self, U, g):
+        """Group g's part of a batch state array (flat)."""
+        view, off = self.groups[g]
+        return U[off:off + view.state_len]
+
+    def step(self, U, R, nsteps=1, step0=0, stream=None):
+        B.check(B.lib().dgpyr_batch_step(self._h, _dptr(U, self.state_len, "U"),
+                                         _dptr(R, self.state_len, "R"), int(step0), int(nsteps),
+                                         _stream_handle(stream)), "dgpyr_batch_step")
+        return U, R
+
+    def tune(self, nsteps=2, stream=None):
+        """Autotune the work shape of every group; returns the choice per group."""
+        out = (ctypes.c_int32 * self.ngroups)()
+        B.check(B.lib().dgpyr_batch_tune(self._h, int(nsteps), _stream_handle(stream), out),
+                "dgpyr_batch_tune")
+        return list(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for view, _ in getattr(self, "groups", []):
+                view.close()
+            B.lib().dgpyr_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -27,6 +27,8 @@ EXPORTS = (
     "dgpyr_step", "dgpyr_step_timed", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
     "dgpyr_host_mesh", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
+    "dgpyr_batch_setup", "dgpyr_batch_info", "dgpyr_batch_problem", "dgpyr_batch_group",
+    "dgpyr_batch_step", "dgpyr_batch_tune", "dgpyr_batch_destroy",
 )
 
 
@@ -41,6 +43,14 @@ class Mesh(ctypes.Structure):
         ("bc", c_int32),
         ("nsources", c_int32),
         ("sources", POINTER(c_double)),
+    ]
+
+
+class BatchSlot(ctypes.Structure):
+    _fields_ = [
+        ("group", c_int32), ("N", c_int32), ("Np", c_int32), ("reserved", c_int32),
+        ("nelems", c_int64), ("elem_offset", c_int64), ("offset", c_int64), ("len", c_int64),
+        ("dt", c_double), ("inv_length_max", c_double),
     ]
 
 
@@ -104,6 +114,21 @@ def lib():
         getattr(L, name).restype = c_int32
     L.dgpyr_destroy.argtypes = [c_void_p]
     L.dgpyr_destroy.restype = None
+    L.dgpyr_batch_setup.argtypes = [POINTER(Mesh), POINTER(c_int32), POINTER(c_double), c_double,
+                                    c_int32, POINTER(Opts), POINTER(c_void_p)]
+    L.dgpyr_batch_setup.restype = c_int32
+    L.dgpyr_batch_info.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int32)]
+    L.dgpyr_batch_info.restype = c_int32
+    L.dgpyr_batch_problem.argtypes = [c_void_p, c_int32, POINTER(BatchSlot)]
+    L.dgpyr_batch_problem.restype = c_int32
+    L.dgpyr_batch_group.argtypes = [c_void_p, c_int32, POINTER(c_void_p), POINTER(c_int64)]
+    L.dgpyr_batch_group.restype = c_int32
+    L.dgpyr_batch_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]
+    L.dgpyr_batch_step.restype = c_int32
+    L.dgpyr_batch_tune.argtypes = [c_void_p, c_int32, c_void_p, POINTER(c_int32)]
+    L.dgpyr_batch_tune.restype = c_int32
+    L.dgpyr_batch_destroy.argtypes = [c_void_p]
+    L.dgpyr_batch_destroy.restype = None
     L.dgpyr_status_string.argtypes = [c_int32]
     L.dgpyr_status_string.restype = c_char_p
     L.dgpyr_last_error.argtypes = []

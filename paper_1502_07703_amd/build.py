@@ -26,6 +26,7 @@ SOURCES = [
     "kernels_aux.hip",
     "kernels_sf.hip",
     "kernels_bf16.hip",
+    "batch.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

@@ -12,8 +12,10 @@
 #include "dgpyr.h"
 #include "host/mesh.hpp"
 #include "host/refops.hpp"
+#include "internal.hpp"
 
-namespace {
+namespace dgpyr {
+namespace api {
 
 thread_local std::string g_err;
 
@@ -28,25 +30,21 @@ dgpyr_status hip_fail(hipError_t e, const char* what) {
 }
 
 // Carpenter-Kennedy 2N-storage RK(5,4) coefficients.
-const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+extern const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
                         -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
-const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+extern const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                         1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                         2277821191437.0 / 14882151754819.0};
 
-// Stage times c_s of the scheme: the value of U at the start of stage s when
-// integrating U' = 1 from 0 with dt = 1 (consistent with A, B to the last bit).
-struct StageTimes {
-  double c[5];
-  StageTimes() {
-    double u = 0.0, r = 0.0;
-    for (int s = 0; s < 5; ++s) {
-      c[s] = u;
-      r = kRkA[s] * r + 1.0;
-      u += kRkB[s] * r;
-    }
+StageTimes::StageTimes() {
+  double u = 0.0, r = 0.0;
+  for (int s = 0; s < 5; ++s) {
+    c[s] = u;
+    r = kRkA[s] * r + 1.0;
+    u += kRkB[s] * r;
   }
-};
+}
+extern const StageTimes kRkC;
 const StageTimes kRkC;
 
 template <typename T>
@@ -135,12 +133,14 @@ struct LaunchTimer {
 };
 
 // Default 4-element groups per wave of the fused matrix-core kernels.
-// Measured at 384000 pyramids, N = 4: two groups cut the FP64 stage from
-// 3.69 to 3.47 ms and the trace from 0.89 to 0.76 ms, but slow the FP32 stage
-// (2.84 -> 3.04 ms); for N >= 5 two FP64 groups no longer fit the registers
-// of two waves per SIMD.
+// Default 4-element groups per wave of the fused stage kernel.  Measured at
+// 384000 pyramids, N = 4: one group compiled for three waves per SIMD takes
+// 3.09 ms (FP64) and 2.47 ms (FP32) against 3.37 ms and 2.89 ms for two
+// groups at two waves per SIMD.
 int default_groups(int N, int precision) {
-  return (precision == DGPYR_FP64 && N <= 4) ? 2 : 1;
+  (void)N;
+  (void)precision;
+  return 1;
 }
 
 // Kernel kinds per path, in dgpyr_step_timed order.
@@ -334,7 +334,10 @@ dgpyr_status check_ctx(const dgpyr_ctx* c) {
   return DGPYR_OK;
 }
 
-}  // namespace
+}  // namespace api
+}  // namespace dgpyr
+
+using namespace dgpyr::api;
 
 extern "C" {
 
@@ -357,7 +360,8 @@ const char* dgpyr_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
 
-namespace {
+namespace dgpyr {
+namespace api {
 
 // Setup shared by dgpyr_setup and the batch: dtscale (optional, [K]) is the
 // per-element time-step scale; src_range (optional) limits each source's
@@ -423,6 +427,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   }
   if (dtscale)
     for (int64_t e = 0; e < md.K; ++e) md.mat[4 * e + 3] = dtscale[e];
+  c->mat_host = md.mat;
   c->N = N;
   c->Np = ops.Np;
   c->Nc = ops.Nc;
@@ -433,6 +438,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   c->bc = mesh->bc;
   c->alpha = opts->alpha;
   c->inv_length_max = md.inv_length_max;
+  c->inv_length = md.inv_length;
   c->hex_groups = md.hex_groups;
   c->reference_kernels = (opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) != 0;
   c->unfused = (opts->flags & DGPYR_FLAG_UNFUSED) != 0;
@@ -505,7 +511,8 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   return DGPYR_OK;
 }
 
-}  // namespace
+}  // namespace api
+}  // namespace dgpyr
 
 extern "C" {
 

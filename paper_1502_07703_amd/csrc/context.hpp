@@ -123,6 +123,10 @@ struct dgpyr_ctx {
   int nsrc = 0;
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
+  // host copies kept for batches (per-problem time steps): c_K |dK| / |K| and
+  // the material rows [K][4] whose last entry scales the time step
+  std::vector<double> inv_length;
+  std::vector<double> mat_host;
 };
 
 namespace dgpyr {

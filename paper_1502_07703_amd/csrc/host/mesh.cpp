@@ -153,6 +153,7 @@ int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nel
   // is bilinear in (a, b) and constant in c (Lemma 1).  Also |dK| / |K|.
   const int n1 = ops.Nq1;
   md.inv_length_max = 0.0;
+  md.inv_length.assign((size_t)K, 0.0);
   for (int64_t e = 0; e < K; ++e) {
     const double* x = &md.verts[(size_t)e * 16];
     const double r = rho ? rho[e] : 1.0;
@@ -200,7 +201,8 @@ int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nel
       pyr_face_normal(x, f, 0.0, 0.0, nrm);
       area += 2.0 * std::sqrt(dot3(nrm, nrm));  // parameter-space area of a triangle is 2
     }
-    md.inv_length_max = std::max(md.inv_length_max, std::sqrt(k / r) * area / vol);
+    md.inv_length[(size_t)e] = std::sqrt(k / r) * area / vol;
+    md.inv_length_max = std::max(md.inv_length_max, md.inv_length[(size_t)e]);
   }
 
   // Faces: sort by vertex set, pair equal keys.

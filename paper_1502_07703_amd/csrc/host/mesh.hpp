@@ -22,6 +22,7 @@ struct MeshData {
   std::vector<int32_t> conn;
   std::vector<double> mat;
   double inv_length_max = 0.0;  // max_K c_K |dK| / |K|
+  std::vector<double> inv_length;  // [K] c_K |dK| / |K|
   bool hex_groups = false;
   // point sources: src_of [K] (-1 = none), src_phi [nsrc][Np], src_par [nsrc][4]
   std::vector<int32_t> src_of;

@@ -1,0 +1,44 @@
+// Library-internal entry points shared by api.hip (single problems) and
+// batch.hip (batches of independent problems).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "context.hpp"
+#include "dgpyr.h"
+
+namespace dgpyr {
+namespace api {
+
+// Records msg as the thread's last error and returns s.
+dgpyr_status fail(dgpyr_status s, const std::string& msg);
+dgpyr_status hip_fail(hipError_t e, const char* what);
+dgpyr_status check_ctx(const dgpyr_ctx* c);
+
+// Carpenter-Kennedy RK(5,4) 2N-storage coefficients and the stage times c_s.
+extern const double kRkA[5];
+extern const double kRkB[5];
+struct StageTimes {
+  double c[5];
+  StageTimes();
+};
+extern const StageTimes kRkC;
+
+struct LaunchTimer;
+
+// One LSRK stage (mode 1) or right-hand side (mode 0) on stream s.
+hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, double* R, double ra,
+                     double rb, double dt, hipStream_t s, LaunchTimer* tm);
+
+// Context setup; dtscale ([K], optional) scales the time step per element,
+// src_range ([nsources][2], optional) limits each source's element search.
+dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts,
+                        const double* dtscale, const int64_t* src_range, dgpyr_ctx** out);
+
+// Releases a context and its device memory.
+void free_ctx(dgpyr_ctx* c);
+
+}  // namespace api
+}  // namespace dgpyr

@@ -278,8 +278,19 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 // only wave-local ordering.  In RK mode the kernel reads and writes only its
 // own elements' U and R; other workgroups read traces (T), never U, so the
 // in-place update is safe.
+// Waves per SIMD the fused stage kernel is compiled for: the largest count
+// whose register budget (512 / waves) holds the kernel without spilling
+// (checked on the gfx950 build: FP64 N = 4, one group: 150 registers for three
+// waves against 200 when unconstrained).
+template <int N, int FORM, int G>
+struct StageWaves {
+  static constexpr int value =
+      G == 2 ? (FORM == 0 ? (N <= 4 ? 2 : 1) : (N <= 6 ? 2 : 1))
+             : (FORM == 0 ? (N <= 4 ? 3 : N == 5 ? 2 : 1) : (N <= 6 ? 3 : 2));
+};
+
 template <int N, int FORM, int MODE, int G>
-__global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restrict__ U,
+__global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_stage_mfma(const double* __restrict__ U,
                                                        const double* __restrict__ T, FragOps fo,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {
@@ -444,8 +455,11 @@ __global__ __launch_bounds__(kBlock, G) void k_stage_mfma(const double* __restri
   }
 }
 
-// Element groups per wave for the fused stage and the trace (1 or 2).
+// Element groups per wave of the fused stage (1 or 2, set per context) and of
+// the trace (2 up to N = 5: measured at N = 4, 0.74 ms against 0.82 ms for one
+// group; above, two groups need more registers than four waves per SIMD leave).
 inline int mfma_groups(const dgpyr_ctx& c) { return c.mfma_groups == 2 ? 2 : 1; }
+inline int trace_groups(const dgpyr_ctx& c) { return c.N <= 5 ? 2 : 1; }
 
 template <int N, int FORM, int G>
 hipError_t stage_mfma_n(const dgpyr_ctx& c, int mode, const double* U, const double* T, double* out,
@@ -482,7 +496,7 @@ hipError_t trace_mfma_g(const dgpyr_ctx& c, const double* U, double* T, hipStrea
 
 template <int N>
 hipError_t trace_mfma_n(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
-  return mfma_groups(c) == 2 ? trace_mfma_g<N, 2>(c, U, T, s) : trace_mfma_g<N, 1>(c, U, T, s);
+  return trace_groups(c) == 2 ? trace_mfma_g<N, 2>(c, U, T, s) : trace_mfma_g<N, 1>(c, U, T, s);
 }
 
 template <int N, int FORM>

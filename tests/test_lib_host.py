@@ -150,8 +150,23 @@ def test_setup_errors_before_device(B):
     with pytest.raises(dg.DgpyrError) as ex:
         dg.Solver(xyz, e2v, 2, sum_factorized=True)
     assert ex.value.status == B.E_UNSUPPORTED
+    # batch arguments are checked before any device work
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Batch([dict(xyz=xyz, e2v=e2v, N=9)])
+    assert ex.value.status == B.E_ORDER
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Batch([dict(xyz=xyz, e2v=e2v, N=2)], cfl=0.0)
+    assert ex.value.status == B.E_ARG
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Batch([dict(xyz=xyz, e2v=e2v, N=2)], dts=[-1.0])
+    assert ex.value.status == B.E_ARG
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Batch([])
+    assert ex.value.status == B.E_ARG
     # calls on a missing context fail without touching a device
     L = B.lib()
+    assert L.dgpyr_batch_step(None, None, None, 0, 1, None) != 0
+    assert L.dgpyr_batch_info(None, None, None) != 0
     assert L.dgpyr_set_groups(None, 1) != 0
     assert L.dgpyr_set_groups(None, 3) != 0
 
