@@ -248,6 +248,13 @@ void dgpyr_batch_destroy(dgpyr_batch* b);
 dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,
                                   int64_t* needed);
 
+/* Host-only location of the mesh's point sources (what dgpyr_setup does
+ * before touching the device): elem[s] (optional, [nsources]) receives the
+ * containing element and abc (optional, [nsources][3]) the collapsed
+ * coordinates (a, b, c) of the point there.  Errors as dgpyr_setup's host
+ * part; E_ARG without sources or when a point lies in no element. */
+dgpyr_status dgpyr_host_sources(const dgpyr_mesh* mesh, int32_t N, int64_t* elem, double* abc);
+
 /* Host-only run of the mesh builders (geometry checks and face matching) that
  * dgpyr_setup performs before touching the device.  nbr (optional, [nelems][5])
  * receives the neighbour element of each face or -1; inv_length_max and

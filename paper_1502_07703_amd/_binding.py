@@ -25,7 +25,7 @@ FLAG_SUM_FACTORIZED = 4
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
     "dgpyr_step", "dgpyr_step_timed", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
-    "dgpyr_host_mesh", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
+    "dgpyr_host_mesh", "dgpyr_host_sources", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
     "dgpyr_batch_setup", "dgpyr_batch_info", "dgpyr_batch_problem", "dgpyr_batch_group",
     "dgpyr_batch_step", "dgpyr_batch_tune", "dgpyr_batch_destroy",
@@ -109,6 +109,8 @@ def lib():
     L.dgpyr_host_mesh.argtypes = [POINTER(Mesh), c_int32, POINTER(c_int32), POINTER(c_double),
                                   POINTER(c_int32)]
     L.dgpyr_host_mesh.restype = c_int32
+    L.dgpyr_host_sources.argtypes = [POINTER(Mesh), c_int32, POINTER(c_int64), POINTER(c_double)]
+    L.dgpyr_host_sources.restype = c_int32
     for name in ("dgpyr_volume_points", "dgpyr_project", "dgpyr_eval"):
         getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         getattr(L, name).restype = c_int32

@@ -709,6 +709,28 @@ dgpyr_status dgpyr_host_mesh(const dgpyr_mesh* mesh, int32_t N, int32_t* nbr,
   return DGPYR_OK;
 }
 
+dgpyr_status dgpyr_host_sources(const dgpyr_mesh* mesh, int32_t N, int64_t* elem, double* abc) {
+  if (!mesh || !mesh->xyz || !mesh->e2v || mesh->nverts <= 0 || mesh->nelems <= 0)
+    return fail(DGPYR_E_ARG, "mesh arrays must be non-null with positive sizes");
+  if (mesh->nsources <= 0 || !mesh->sources) return fail(DGPYR_E_ARG, "no sources");
+  if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
+  dgpyr::RefOps ops;
+  char msg[256];
+  if (!dgpyr::build_refops(N, ops, msg, sizeof msg)) return fail(DGPYR_E_STATE, msg);
+  dgpyr::MeshData md;
+  std::string err;
+  int rc = dgpyr::build_mesh(ops, mesh->nverts, mesh->xyz, mesh->nelems, mesh->e2v, mesh->rho,
+                             mesh->kappa, md, err);
+  if (rc == 0) rc = dgpyr::locate_sources(ops, mesh->nsources, mesh->sources, nullptr, md, err);
+  if (rc != 0) return fail((dgpyr_status)rc, err);
+  for (int s = 0; s < mesh->nsources; ++s) {
+    if (elem) elem[s] = md.src_elem[(size_t)s];
+    if (abc)
+      for (int k = 0; k < 3; ++k) abc[3 * s + k] = md.src_abc[(size_t)3 * s + k];
+  }
+  return DGPYR_OK;
+}
+
 dgpyr_status dgpyr_volume_points(dgpyr_ctx* c, double* xyz, double* wJ, void* stream) {
   if (dgpyr_status s = check_ctx(c)) return s;
   if (!xyz) return fail(DGPYR_E_ARG, "xyz is null");

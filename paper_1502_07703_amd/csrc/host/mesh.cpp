@@ -45,6 +45,8 @@ int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t
   md.src_of.assign((size_t)md.K, -1);
   md.src_phi.assign((size_t)nsrc * ops.Np, 0.0);
   md.src_par.assign((size_t)nsrc * 4, 0.0);
+  md.src_elem.assign((size_t)nsrc, -1);
+  md.src_abc.assign((size_t)nsrc * 3, 0.0);
   for (int s = 0; s < nsrc; ++s) {
     const double* xs = src + 6 * s;
     int64_t found = -1;
@@ -65,7 +67,7 @@ int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t
       if (!inbox) continue;
       // Newton on x(a,b,c) = (1-c)/2 B(a,b) + (1+c)/2 x4 from the element middle
       double a = 0.0, b = 0.0, c = -0.5;
-      bool ok = false;
+      bool ok = false, polish = false;
       for (int it = 0; it < 60; ++it) {
         double B[3], Ba[3], Bb[3], F[3], G[9];
         for (int d = 0; d < 3; ++d) {
@@ -95,10 +97,14 @@ int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t
         b += dl[1];
         c += dl[2];
         if (std::fabs(a) > 10 || std::fabs(b) > 10 || std::fabs(c) > 10) break;
-        if (std::fabs(dl[0]) + std::fabs(dl[1]) + std::fabs(dl[2]) < 1e-15) {
+        // Steps stall at a few ulps of O(1) coordinates (more where the map
+        // is ill-conditioned); a step below 1e-12 has converged, and one more
+        // step polishes the root to rounding.
+        if (polish) {
           ok = true;
           break;
         }
+        if (std::fabs(dl[0]) + std::fabs(dl[1]) + std::fabs(dl[2]) < 1e-12) polish = true;
       }
       const double sl = 1e-10;
       if (ok && a >= -1 - sl && a <= 1 + sl && b >= -1 - sl && b <= 1 + sl && c >= -1 - sl &&
@@ -119,6 +125,10 @@ int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t
       return DGPYR_E_UNSUPPORTED;
     }
     md.src_of[(size_t)found] = s;
+    md.src_elem[(size_t)s] = found;
+    md.src_abc[(size_t)3 * s + 0] = fa;
+    md.src_abc[(size_t)3 * s + 1] = fb;
+    md.src_abc[(size_t)3 * s + 2] = fc;
     eval_basis(ops.N, fa, fb, fc, &md.src_phi[(size_t)s * ops.Np]);
     md.src_par[4 * s + 0] = xs[3];
     md.src_par[4 * s + 1] = xs[4];

@@ -27,6 +27,8 @@ struct MeshData {
   // point sources: src_of [K] (-1 = none), src_phi [nsrc][Np], src_par [nsrc][4]
   std::vector<int32_t> src_of;
   std::vector<double> src_phi, src_par;
+  std::vector<int64_t> src_elem;  // [nsrc] containing element
+  std::vector<double> src_abc;    // [nsrc][3] collapsed coordinates there
   int nsrc = 0;
 };
 

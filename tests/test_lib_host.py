@@ -231,3 +231,46 @@ def test_sum_factorisation_tables_rebuild_dense_operators(B, N):
     for X, Y in ((V, V2), (Dr, Dr2), (Ds, Ds2), (Dt, Dt2)):
         assert np.abs(X - Y.reshape(-1, Np)).max() <= 1e-12 * max(1.0, np.abs(X).max())
     assert np.abs(Vf - F2).max() <= 1e-12 * max(1.0, np.abs(Vf).max())
+
+
+def test_source_location_matches_oracle(B):
+    """Host location of point sources (Newton on the collapsed map) against the
+    oracle's independent search, on perturbed meshes and many random points --
+    among them a point whose Newton steps stall at a few ulps above 1e-15."""
+    import ctypes
+
+    import paper_1502_07703_amd as dg
+    from oracle.dg import locate_point
+    cases = [(17, 4005, [[0.567811726463066, 0.6555454856775709, 0.5719857743358235]])]
+    rng = np.random.default_rng(3)
+    for k1d, seed in ((3, 1), (4, 2)):
+        cases.append((k1d, seed, rng.uniform(0.02, 0.98, (40, 3)).tolist()))
+    for k1d, seed, pts in cases:
+        xyz, e2v = hex_pyramid_mesh(k1d, seed=seed)
+        src = np.array([[*p, 1.0, 10.0, 0.0] for p in pts])
+        h = dg._HostMesh(xyz, e2v, sources=src)
+        n = len(pts)
+        elem = np.zeros(n, np.int64)
+        abc = np.zeros((n, 3))
+        st = B.lib().dgpyr_host_sources(ctypes.byref(h.struct), 2,
+                                        elem.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        abc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if st == B.E_UNSUPPORTED:  # two random points in one element: test them one by one
+            for j, p in enumerate(pts):
+                h1 = dg._HostMesh(xyz, e2v, sources=src[j:j + 1])
+                e1 = np.zeros(1, np.int64)
+                a1 = np.zeros(3)
+                B.check(B.lib().dgpyr_host_sources(
+                    ctypes.byref(h1.struct), 2, e1.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                    a1.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "host sources")
+                elem[j], abc[j] = e1[0], a1
+        else:
+            B.check(st, "host sources")
+        for j, p in enumerate(pts):
+            r, ok = locate_point(xyz[e2v[elem[j]]], np.array(p))
+            assert ok, (k1d, j)
+            # oracle reference coordinates (r, s, t) -> collapsed (a, b, c)
+            t = r[2]
+            a = 2 * (1 + r[0]) / (1 - t) - 1
+            b = 2 * (1 + r[1]) / (1 - t) - 1
+            assert np.allclose(abc[j], [a, b, t], atol=1e-10), (k1d, j, abc[j], (a, b, t))
