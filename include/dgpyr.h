@@ -164,6 +164,16 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* ctx, double* U, double* R, double t0, d
  * order used by dgpyr_step_timed; the string lives as long as the context. */
 const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
 
+/* Transposed operator for the discrete adjoint (Sections 4.1-4.3 read as
+ * dU/dt = A U + b, A = -Kmat M^-1 (volume + surface), Kmat = kappa on
+ * pressure rows and 1/rho on velocity rows): out = A^T lam, exactly the
+ * transpose of what dgpyr_rhs applies (without sources), for any flux alpha
+ * and boundary condition.  lam, out: device state arrays (may not alias).
+ * FP64 matrix-core kernels in every precision form.  The first call
+ * allocates one state-sized scratch array held by the context.
+ * Asynchronous. */
+dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* ctx, const double* lam, double* out, void* stream);
+
 /* Work shape of the fused matrix-core stage kernel (FP64 and FP32 forms):
  * groups_per_wave = number of 4-element groups one wave owns, so that each
  * operator fragment loaded feeds that many matrix-core products (the trace

@@ -148,6 +148,14 @@ class Solver:
                                   _stream_handle(stream)), "dgpyr_rhs")
         return out
 
+    def adjoint_rhs(self, lam, out=None, stream=None):
+        """A^T lam: the transpose of the operator rhs() applies (no sources)."""
+        out = self.empty_state() if out is None else out
+        B.check(B.lib().dgpyr_adjoint_rhs(self._h, _dptr(lam, self.state_len, "lam"),
+                                          _dptr(out, self.state_len, "out"),
+                                          _stream_handle(stream)), "dgpyr_adjoint_rhs")
+        return out
+
     def step(self, U, R, dt, nsteps=1, t0=0.0, stream=None):
         B.check(B.lib().dgpyr_step(self._h, _dptr(U, self.state_len, "U"),
                                    _dptr(R, self.state_len, "R"), float(t0), float(dt),

@@ -24,7 +24,7 @@ FLAG_SUM_FACTORIZED = 4
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
-    "dgpyr_step", "dgpyr_step_timed", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
+    "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
     "dgpyr_host_mesh", "dgpyr_host_sources", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
     "dgpyr_batch_setup", "dgpyr_batch_info", "dgpyr_batch_problem", "dgpyr_batch_group",
@@ -100,6 +100,8 @@ def lib():
     L.dgpyr_step_timed.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int32,
                                    c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]
     L.dgpyr_step_timed.restype = c_int32
+    L.dgpyr_adjoint_rhs.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    L.dgpyr_adjoint_rhs.restype = c_int32
     L.dgpyr_set_groups.argtypes = [c_void_p, c_int32]
     L.dgpyr_set_groups.restype = c_int32
     L.dgpyr_kernel_names.argtypes = [c_void_p]

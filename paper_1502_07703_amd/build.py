@@ -27,6 +27,7 @@ SOURCES = [
     "kernels_sf.hip",
     "kernels_bf16.hip",
     "batch.hip",
+    "kernels_adjoint.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

@@ -482,6 +482,14 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
     st = c->precision == DGPYR_SPLIT_BF16 ? upload_bf16(c, ops)
          : c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops)
                                            : upload_frags<double>(c, ops);
+  {  // FP64 fragments of the transposed operator
+    const double* pd = nullptr;
+    if (st == DGPYR_OK && (st = upload(c, frag_rows<double>(ops.V, ops.Nc, ops.Np), &pd, "VrF")) == DGPYR_OK) c->adj.VrF = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Dr, ops.Nc, ops.Np), &pd, "DrP")) == DGPYR_OK) c->adj.DrP = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Ds, ops.Nc, ops.Np), &pd, "DsP")) == DGPYR_OK) c->adj.DsP = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Dt, ops.Nc, ops.Np), &pd, "DtP")) == DGPYR_OK) c->adj.DtP = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Vf, ops.Nfc, ops.Np), &pd, "LfP")) == DGPYR_OK) c->adj.LfP = pd;
+  }
   if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
   if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
   if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
@@ -626,6 +634,22 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, dou
   if (tm.err != hipSuccess) return hip_fail(tm.err, "event timing");
   hipError_t e = hipStreamSynchronize(s);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "stream synchronize");
+}
+
+dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* c, const double* lam, double* out, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!lam || !out) return fail(DGPYR_E_ARG, "null array");
+  if ((const double*)out == lam) return fail(DGPYR_E_ARG, "lam and out must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->adj_mu) {
+    if (dgpyr_status st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->adj_mu,
+                                "adjoint scratch"))
+      return st;
+  }
+  hipError_t e = dgpyr::launch_adjoint_scale(*c, lam, c->adj_mu, s);
+  if (e == hipSuccess) e = dgpyr::launch_trace_mfma(*c, c->adj_mu, c->T, s);
+  if (e == hipSuccess) e = dgpyr::launch_adjoint(*c, c->adj_mu, c->T, out, s);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "adjoint launch");
 }
 
 dgpyr_status dgpyr_set_groups(dgpyr_ctx* c, int32_t groups) {

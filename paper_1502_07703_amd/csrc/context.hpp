@@ -52,6 +52,18 @@ struct FragOps {
   const void* LfF;
 };
 
+// FP64 fragments of the transposed operator (kernels_adjoint.hip), packed as
+// FragOps:  VrF [NTC][NCHP][64][2]: V in the derivative layout (interpolation),
+// DrP, DsP, DtP [NTC][4][NITP][64][2]: D_rho in the projection layout, LfP the
+// lift (V^f) in the projection layout.
+struct AdjOps {
+  const double* VrF;
+  const double* DrP;
+  const double* DsP;
+  const double* DtP;
+  const double* LfP;
+};
+
 // Split-BF16 operator fragments (hi and lo parts, bf16 bit patterns), for
 // v_mfma_f32_16x16x32_bf16.  Derivative operators, chunk c of 32 basis
 // functions, tile t of 16 points:  [t][c][64][8]: D[16t + l%16][32c + 8(l/16) + j];
@@ -110,6 +122,8 @@ struct dgpyr_ctx {
   dgpyr::DevOps ops{};
   dgpyr::DevMesh mesh{};
   dgpyr::FragOps frag{};
+  dgpyr::AdjOps adj{};
+  double* adj_mu = nullptr;  // M^-1 Kmat lam scratch, allocated on first adjoint use
   bool reference_kernels = false;  // plain FP64 VALU kernels instead of MFMA
   bool unfused = false;            // separate matrix-core volume and surface launches
   bool sum_factorized = false;     // FP64 sum-factorised kernels
@@ -140,6 +154,10 @@ hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const d
 // Initial data and evaluation (kernels_aux.hip).
 hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s);
 hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s);
+// Transposed operator (kernels_adjoint.hip).
+hipError_t launch_adjoint_scale(const dgpyr_ctx& c, const double* lam, double* mu, hipStream_t s);
+hipError_t launch_adjoint(const dgpyr_ctx& c, const double* mu, const double* T, double* out,
+                          hipStream_t s);
 hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s);
 hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s);
 // Matrix-core kernels (kernels_mfma.hip).
