@@ -174,6 +174,35 @@ const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
  * Asynchronous. */
 dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* ctx, const double* lam, double* out, void* stream);
 
+/* ---- Discrete adjoint: gradient of a receiver misfit w.r.t. kappa --------
+ * New per-element bulk modulus kappa = rho c^2 (host array [nelems], rho
+ * unchanged; impedances follow).  Synchronous. */
+dgpyr_status dgpyr_set_kappa(dgpyr_ctx* ctx, const double* kappa);
+
+/* Receiver points (host xyz [nrec][3]), located on the host in the element
+ * (lowest index) containing each; several may share an element.  Allocates
+ * device memory held by the context.  E_ARG for a point in no element. */
+dgpyr_status dgpyr_set_receivers(dgpyr_ctx* ctx, int32_t nrec, const double* xyz);
+
+/* Pressure at the receivers: out[r] = sum_i phi_i(xi_r) U[e_r][p][i]
+ * (device out [nrec]).  Asynchronous. */
+dgpyr_status dgpyr_receivers_sample(dgpyr_ctx* ctx, const double* U, double* out, void* stream);
+
+/* Adjoint of the sampling: Ubar[e_r][p][i] += coef[r] phi_i(xi_r) (device coef
+ * [nrec]).  Asynchronous. */
+dgpyr_status dgpyr_receivers_inject(dgpyr_ctx* ctx, double* Ubar, const double* coef,
+                                    void* stream);
+
+/* Reverse of one LSRK(5,4) step (Algorithm 3) of size dt from time t0 whose
+ * initial state is U0: on entry Ubar is the adjoint of the step's final
+ * state, on exit that of U0; grad [nelems] accumulates the step's part of
+ * dJ/dkappa.  The five stage inputs are recomputed from U0 (sources
+ * included).  Central flux only: E_UNSUPPORTED for alpha != 0.  The first
+ * call allocates nine state-sized scratch arrays held by the context.
+ * Device arrays; asynchronous. */
+dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* ctx, const double* U0, double* Ubar, double* grad,
+                                double t0, double dt, void* stream);
+
 /* Work shape of the fused matrix-core stage kernel (FP64 and FP32 forms):
  * groups_per_wave = number of 4-element groups one wave owns, so that each
  * operator fragment loaded feeds that many matrix-core products (the trace

@@ -27,6 +27,12 @@ def LSRK_CFL_CONSTANT(N: int) -> float:
     return 2.0 * (N + 1) * (N + 3) / 3.0
 
 
+def _to_numpy(x):
+    if hasattr(x, "detach"):
+        return x.detach().cpu().numpy()
+    return np.asarray(x)
+
+
 def _stream_handle(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -155,6 +161,41 @@ class Solver:
                                           _dptr(out, self.state_len, "out"),
                                           _stream_handle(stream)), "dgpyr_adjoint_rhs")
         return out
+
+    # -- discrete adjoint ---------------------------------------------------------
+    def set_kappa(self, kappa):
+        """New per-element bulk modulus (host or device array of nelems values)."""
+        k = np.ascontiguousarray(_to_numpy(kappa), dtype=np.float64)
+        if k.shape != (self.K,):
+            raise ValueError(f"kappa must have shape ({self.K},)")
+        B.check(B.lib().dgpyr_set_kappa(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                "dgpyr_set_kappa")
+
+    def set_receivers(self, points):
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        B.check(B.lib().dgpyr_set_receivers(self._h, pts.shape[0],
+                                            pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                "dgpyr_set_receivers")
+        self.nrec = pts.shape[0]
+
+    def sample_receivers(self, U, out, stream=None):
+        B.check(B.lib().dgpyr_receivers_sample(self._h, _dptr(U, self.state_len, "U"),
+                                               _dptr(out, self.nrec, "out"),
+                                               _stream_handle(stream)), "dgpyr_receivers_sample")
+        return out
+
+    def inject_receivers(self, Ubar, coef, stream=None):
+        B.check(B.lib().dgpyr_receivers_inject(self._h, _dptr(Ubar, self.state_len, "Ubar"),
+                                               _dptr(coef, self.nrec, "coef"),
+                                               _stream_handle(stream)), "dgpyr_receivers_inject")
+        return Ubar
+
+    def adjoint_step(self, U0, Ubar, grad, t0, dt, stream=None):
+        B.check(B.lib().dgpyr_adjoint_step(self._h, _dptr(U0, self.state_len, "U0"),
+                                           _dptr(Ubar, self.state_len, "Ubar"),
+                                           _dptr(grad, self.K, "grad"), float(t0), float(dt),
+                                           _stream_handle(stream)), "dgpyr_adjoint_step")
+        return Ubar, grad
 
     def step(self, U, R, dt, nsteps=1, t0=0.0, stream=None):
         B.check(B.lib().dgpyr_step(self._h, _dptr(U, self.state_len, "U"),

@@ -24,7 +24,9 @@ FLAG_SUM_FACTORIZED = 4
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
-    "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
+    "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_set_kappa",
+    "dgpyr_set_receivers", "dgpyr_receivers_sample", "dgpyr_receivers_inject",
+    "dgpyr_adjoint_step", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
     "dgpyr_host_mesh", "dgpyr_host_sources", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
     "dgpyr_batch_setup", "dgpyr_batch_info", "dgpyr_batch_problem", "dgpyr_batch_group",
@@ -102,6 +104,16 @@ def lib():
     L.dgpyr_step_timed.restype = c_int32
     L.dgpyr_adjoint_rhs.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     L.dgpyr_adjoint_rhs.restype = c_int32
+    L.dgpyr_set_kappa.argtypes = [c_void_p, POINTER(c_double)]
+    L.dgpyr_set_kappa.restype = c_int32
+    L.dgpyr_set_receivers.argtypes = [c_void_p, c_int32, POINTER(c_double)]
+    L.dgpyr_set_receivers.restype = c_int32
+    for name in ("dgpyr_receivers_sample", "dgpyr_receivers_inject"):
+        getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        getattr(L, name).restype = c_int32
+    L.dgpyr_adjoint_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                     c_void_p]
+    L.dgpyr_adjoint_step.restype = c_int32
     L.dgpyr_set_groups.argtypes = [c_void_p, c_int32]
     L.dgpyr_set_groups.restype = c_int32
     L.dgpyr_kernel_names.argtypes = [c_void_p]

@@ -28,6 +28,7 @@ SOURCES = [
     "kernels_bf16.hip",
     "batch.hip",
     "kernels_adjoint.hip",
+    "adjoint.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

@@ -428,6 +428,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   if (dtscale)
     for (int64_t e = 0; e < md.K; ++e) md.mat[4 * e + 3] = dtscale[e];
   c->mat_host = md.mat;
+  c->verts_host = md.verts;
   c->N = N;
   c->Np = ops.Np;
   c->Nc = ops.Nc;

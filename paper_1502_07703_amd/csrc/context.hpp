@@ -124,6 +124,14 @@ struct dgpyr_ctx {
   dgpyr::FragOps frag{};
   dgpyr::AdjOps adj{};
   double* adj_mu = nullptr;  // M^-1 Kmat lam scratch, allocated on first adjoint use
+  // reverse-step scratch (allocated on first dgpyr_adjoint_step): stage inputs
+  // W[5], forward R, adjoint R, A^T output, stage right-hand side
+  double* adj_work = nullptr;
+  // receivers (dgpyr_set_receivers): element and basis values phi_r [nrec][Np]
+  int nrec = 0;
+  const int64_t* rec_elem = nullptr;
+  const double* rec_phi = nullptr;
+  std::vector<double> verts_host;  // [K][16], for locating receivers
   bool reference_kernels = false;  // plain FP64 VALU kernels instead of MFMA
   bool unfused = false;            // separate matrix-core volume and surface launches
   bool sum_factorized = false;     // FP64 sum-factorised kernels
@@ -158,6 +166,14 @@ hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s);
 hipError_t launch_adjoint_scale(const dgpyr_ctx& c, const double* lam, double* mu, hipStream_t s);
 hipError_t launch_adjoint(const dgpyr_ctx& c, const double* mu, const double* T, double* out,
                           hipStream_t s);
+hipError_t launch_rec_sample(const dgpyr_ctx& c, const double* U, double* out, hipStream_t s);
+hipError_t launch_rec_inject(const dgpyr_ctx& c, double* Ub, const double* coef, hipStream_t s);
+hipError_t launch_adj_pre(const dgpyr_ctx& c, double* Rb, const double* Ub, double bs,
+                          hipStream_t s);
+hipError_t launch_adj_post(const dgpyr_ctx& c, double* Ub, double* Rb, const double* ATRb,
+                           double dt, double as, hipStream_t s);
+hipError_t launch_kappa_grad(const dgpyr_ctx& c, double* grad, const double* Rb, const double* F,
+                             double dt, hipStream_t s);
 hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s);
 hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s);
 // Matrix-core kernels (kernels_mfma.hip).

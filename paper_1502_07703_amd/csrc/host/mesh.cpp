@@ -38,6 +38,79 @@ inline int corner_of(int a, int b) {
 
 }  // namespace
 
+namespace {
+
+// Lowest element in [e_lo, e_hi) containing point xs (bounding box, then
+// Newton on x(a,b,c) = (1-c)/2 B(a,b) + (1+c)/2 x4 from the element middle);
+// returns the element or -1 and the collapsed coordinates in abc.
+int64_t find_point(const double* verts, const double* xs, int64_t e_lo, int64_t e_hi, double* abc) {
+  for (int64_t e = e_lo; e < e_hi; ++e) {
+    const double* x = verts + (size_t)e * 16;
+    bool inbox = true;
+    for (int d = 0; d < 3 && inbox; ++d) {
+      double lo = x[d], hi = x[d];
+      for (int v = 1; v < 5; ++v) {
+        lo = std::min(lo, x[3 * v + d]);
+        hi = std::max(hi, x[3 * v + d]);
+      }
+      const double pad = 1e-9 * std::max(1.0, hi - lo);
+      inbox = xs[d] >= lo - pad && xs[d] <= hi + pad;
+    }
+    if (!inbox) continue;
+    double a = 0.0, b = 0.0, c = -0.5;
+    bool ok = false, polish = false;
+    for (int it = 0; it < 60; ++it) {
+      double B[3], Ba[3], Bb[3], F[3], G[9];
+      for (int d = 0; d < 3; ++d) {
+        const double x0 = x[d], x1 = x[3 + d], x2 = x[6 + d], x3 = x[9 + d], x4 = x[12 + d];
+        B[d] = 0.25 * ((1 - a) * (1 - b) * x0 + (1 + a) * (1 - b) * x1 + (1 + a) * (1 + b) * x2 +
+                       (1 - a) * (1 + b) * x3);
+        Ba[d] = 0.25 * ((1 - b) * (x1 - x0) + (1 + b) * (x2 - x3));
+        Bb[d] = 0.25 * ((1 - a) * (x3 - x0) + (1 + a) * (x2 - x1));
+        F[d] = 0.5 * (1 - c) * B[d] + 0.5 * (1 + c) * x4 - xs[d];
+        G[3 * d + 0] = 0.5 * (1 - c) * Ba[d];
+        G[3 * d + 1] = 0.5 * (1 - c) * Bb[d];
+        G[3 * d + 2] = 0.5 * (x4 - B[d]);
+      }
+      // solve G delta = -F by Cramer's rule
+      const double det = G[0] * (G[4] * G[8] - G[5] * G[7]) - G[1] * (G[3] * G[8] - G[5] * G[6]) +
+                         G[2] * (G[3] * G[7] - G[4] * G[6]);
+      if (!(std::fabs(det) > 0)) break;
+      double dl[3];
+      for (int k = 0; k < 3; ++k) {
+        double M[9];
+        for (int i = 0; i < 9; ++i) M[i] = G[i];
+        for (int r = 0; r < 3; ++r) M[3 * r + k] = -F[r];
+        dl[k] = (M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+                 M[2] * (M[3] * M[7] - M[4] * M[6])) / det;
+      }
+      a += dl[0];
+      b += dl[1];
+      c += dl[2];
+      if (std::fabs(a) > 10 || std::fabs(b) > 10 || std::fabs(c) > 10) break;
+      // Steps stall at a few ulps of O(1) coordinates (more where the map
+      // is ill-conditioned); a step below 1e-12 has converged, and one more
+      // step polishes the root to rounding.
+      if (polish) {
+        ok = true;
+        break;
+      }
+      if (std::fabs(dl[0]) + std::fabs(dl[1]) + std::fabs(dl[2]) < 1e-12) polish = true;
+    }
+    const double sl = 1e-10;
+    if (ok && a >= -1 - sl && a <= 1 + sl && b >= -1 - sl && b <= 1 + sl && c >= -1 - sl &&
+        c <= 1 + sl) {
+      abc[0] = a;
+      abc[1] = b;
+      abc[2] = c;
+      return e;
+    }
+  }
+  return -1;
+}
+
+}  // namespace
+
 int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t* range,
                    MeshData& md, std::string& err) {
   char buf[256];
@@ -49,70 +122,9 @@ int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t
   md.src_abc.assign((size_t)nsrc * 3, 0.0);
   for (int s = 0; s < nsrc; ++s) {
     const double* xs = src + 6 * s;
-    int64_t found = -1;
-    double fa = 0, fb = 0, fc = 0;
     const int64_t e_lo = range ? range[2 * s] : 0, e_hi = range ? range[2 * s + 1] : md.K;
-    for (int64_t e = e_lo; e < e_hi && found < 0; ++e) {
-      const double* x = &md.verts[(size_t)e * 16];
-      bool inbox = true;
-      for (int d = 0; d < 3 && inbox; ++d) {
-        double lo = x[d], hi = x[d];
-        for (int v = 1; v < 5; ++v) {
-          lo = std::min(lo, x[3 * v + d]);
-          hi = std::max(hi, x[3 * v + d]);
-        }
-        const double pad = 1e-9 * std::max(1.0, hi - lo);
-        inbox = xs[d] >= lo - pad && xs[d] <= hi + pad;
-      }
-      if (!inbox) continue;
-      // Newton on x(a,b,c) = (1-c)/2 B(a,b) + (1+c)/2 x4 from the element middle
-      double a = 0.0, b = 0.0, c = -0.5;
-      bool ok = false, polish = false;
-      for (int it = 0; it < 60; ++it) {
-        double B[3], Ba[3], Bb[3], F[3], G[9];
-        for (int d = 0; d < 3; ++d) {
-          const double x0 = x[d], x1 = x[3 + d], x2 = x[6 + d], x3 = x[9 + d], x4 = x[12 + d];
-          B[d] = 0.25 * ((1 - a) * (1 - b) * x0 + (1 + a) * (1 - b) * x1 + (1 + a) * (1 + b) * x2 +
-                         (1 - a) * (1 + b) * x3);
-          Ba[d] = 0.25 * ((1 - b) * (x1 - x0) + (1 + b) * (x2 - x3));
-          Bb[d] = 0.25 * ((1 - a) * (x3 - x0) + (1 + a) * (x2 - x1));
-          F[d] = 0.5 * (1 - c) * B[d] + 0.5 * (1 + c) * x4 - xs[d];
-          G[3 * d + 0] = 0.5 * (1 - c) * Ba[d];
-          G[3 * d + 1] = 0.5 * (1 - c) * Bb[d];
-          G[3 * d + 2] = 0.5 * (x4 - B[d]);
-        }
-        // solve G delta = -F by Cramer's rule
-        const double det = G[0] * (G[4] * G[8] - G[5] * G[7]) - G[1] * (G[3] * G[8] - G[5] * G[6]) +
-                           G[2] * (G[3] * G[7] - G[4] * G[6]);
-        if (!(std::fabs(det) > 0)) break;
-        double dl[3];
-        for (int k = 0; k < 3; ++k) {
-          double M[9];
-          for (int i = 0; i < 9; ++i) M[i] = G[i];
-          for (int r = 0; r < 3; ++r) M[3 * r + k] = -F[r];
-          dl[k] = (M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
-                   M[2] * (M[3] * M[7] - M[4] * M[6])) / det;
-        }
-        a += dl[0];
-        b += dl[1];
-        c += dl[2];
-        if (std::fabs(a) > 10 || std::fabs(b) > 10 || std::fabs(c) > 10) break;
-        // Steps stall at a few ulps of O(1) coordinates (more where the map
-        // is ill-conditioned); a step below 1e-12 has converged, and one more
-        // step polishes the root to rounding.
-        if (polish) {
-          ok = true;
-          break;
-        }
-        if (std::fabs(dl[0]) + std::fabs(dl[1]) + std::fabs(dl[2]) < 1e-12) polish = true;
-      }
-      const double sl = 1e-10;
-      if (ok && a >= -1 - sl && a <= 1 + sl && b >= -1 - sl && b <= 1 + sl && c >= -1 - sl &&
-          c <= 1 + sl) {
-        found = e;
-        fa = a; fb = b; fc = c;
-      }
-    }
+    double abc[3];
+    const int64_t found = find_point(md.verts.data(), xs, e_lo, e_hi, abc);
     if (found < 0) {
       std::snprintf(buf, sizeof buf, "source %d at (%g, %g, %g) lies in no element", s, xs[0],
                     xs[1], xs[2]);
@@ -126,13 +138,32 @@ int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t
     }
     md.src_of[(size_t)found] = s;
     md.src_elem[(size_t)s] = found;
-    md.src_abc[(size_t)3 * s + 0] = fa;
-    md.src_abc[(size_t)3 * s + 1] = fb;
-    md.src_abc[(size_t)3 * s + 2] = fc;
-    eval_basis(ops.N, fa, fb, fc, &md.src_phi[(size_t)s * ops.Np]);
+    for (int k = 0; k < 3; ++k) md.src_abc[(size_t)3 * s + k] = abc[k];
+    eval_basis(ops.N, abc[0], abc[1], abc[2], &md.src_phi[(size_t)s * ops.Np]);
     md.src_par[4 * s + 0] = xs[3];
     md.src_par[4 * s + 1] = xs[4];
     md.src_par[4 * s + 2] = xs[5] > 0 ? xs[5] : 1.0 / xs[4];
+  }
+  return 0;
+}
+
+int locate_receivers(const RefOps& ops, int nrec, const double* xyz, const double* verts,
+                     int64_t K, std::vector<int64_t>& elem, std::vector<double>& phi,
+                     std::string& err) {
+  elem.assign((size_t)nrec, -1);
+  phi.assign((size_t)nrec * ops.Np, 0.0);
+  for (int r = 0; r < nrec; ++r) {
+    double abc[3];
+    const int64_t e = find_point(verts, xyz + 3 * r, 0, K, abc);
+    if (e < 0) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "receiver %d at (%g, %g, %g) lies in no element", r,
+                    xyz[3 * r], xyz[3 * r + 1], xyz[3 * r + 2]);
+      err = buf;
+      return DGPYR_E_ARG;
+    }
+    elem[(size_t)r] = e;
+    eval_basis(ops.N, abc[0], abc[1], abc[2], &phi[(size_t)r * ops.Np]);
   }
   return 0;
 }

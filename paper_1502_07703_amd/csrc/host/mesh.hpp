@@ -40,6 +40,13 @@ struct MeshData {
 int locate_sources(const RefOps& ops, int nsrc, const double* src, const int64_t* range,
                    MeshData& md, std::string& err);
 
+// Locates receiver points xyz [nrec][3] in the K elements whose vertices are
+// verts [K][16] (several points may share an element): elem [nrec] and phi
+// [nrec][Np] = basis values there.
+int locate_receivers(const RefOps& ops, int nrec, const double* xyz, const double* verts,
+                     int64_t K, std::vector<int64_t>& elem, std::vector<double>& phi,
+                     std::string& err);
+
 // Returns 0 on success or a negative dgpyr_status with a message in err.
 int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nelems,
                const int64_t* e2v, const double* rho, const double* kappa, MeshData& md,

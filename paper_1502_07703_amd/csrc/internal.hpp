@@ -37,6 +37,9 @@ hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, doubl
 dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts,
                         const double* dtscale, const int64_t* src_range, dgpyr_ctx** out);
 
+// Device allocation owned by the context (freed with it).
+dgpyr_status alloc(dgpyr_ctx* c, size_t bytes, double** out, const char* what);
+
 // Releases a context and its device memory.
 void free_ctx(dgpyr_ctx* c);
 

@@ -234,6 +234,60 @@ __global__ __launch_bounds__(kBlock, 2) void k_adjoint_mfma(const double* __rest
   }
 }
 
+// Pressure at receivers: out[r] = sum_i phi_r[i] U[e_r][p][i].
+__global__ void k_rec_sample(const double* __restrict__ U, const int64_t* __restrict__ elem,
+                             const double* __restrict__ phi, int nrec, int Np,
+                             double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrec) return;
+  const double* u = U + elem[r] * 4 * Np;
+  const double* f = phi + (int64_t)r * Np;
+  double acc = 0.0;
+  for (int i = 0; i < Np; ++i) acc += f[i] * u[i];
+  out[r] = acc;
+}
+
+// Ubar[e_r][p][i] += coef[r] phi_r[i]; thread i walks the receivers in order,
+// so receivers sharing an element add without races.
+__global__ void k_rec_inject(double* __restrict__ Ub, const int64_t* __restrict__ elem,
+                             const double* __restrict__ phi, const double* __restrict__ coef,
+                             int nrec, int Np) {
+  const int i = threadIdx.x;
+  if (i >= Np) return;
+  for (int r = 0; r < nrec; ++r) Ub[elem[r] * 4 * Np + i] += coef[r] * phi[(int64_t)r * Np + i];
+}
+
+// Reverse LSRK stage, before the transposed operator: Rb += b_s Ub.
+__global__ void k_adj_pre(double* __restrict__ Rb, const double* __restrict__ Ub, double bs,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) Rb[i] += bs * Ub[i];
+}
+
+// After it: Ub += dt (A^T Rb), then Rb *= a_s.
+__global__ void k_adj_post(double* __restrict__ Ub, double* __restrict__ Rb,
+                           const double* __restrict__ ATRb, double dt, double as, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    Ub[i] += dt * ATRb[i];
+    Rb[i] *= as;
+  }
+}
+
+// grad[e] += dt sum_i Rb[e][p][i] F[e][p][i] / kappa_e (F: the stage's
+// right-hand side; its pressure rows carry the factor kappa_e).
+__global__ void k_kappa_grad(double* __restrict__ grad, const double* __restrict__ Rb,
+                             const double* __restrict__ F, const double* __restrict__ mat,
+                             int64_t K, int Np, double dt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= K) return;
+  const double* r = Rb + e * 4 * Np;
+  const double* f = F + e * 4 * Np;
+  double acc = 0.0;
+  for (int i = 0; i < Np; ++i) acc += r[i] * f[i];
+  grad[e] += dt * acc / mat[e * 4];
+}
+
 template <int N>
 hipError_t adjoint_n(const dgpyr_ctx& c, const double* mu, const double* T, double* out,
                      hipStream_t s) {
@@ -274,6 +328,43 @@ hipError_t launch_adjoint_scale(const dgpyr_ctx& c, const double* lam, double* m
 hipError_t launch_adjoint(const dgpyr_ctx& c, const double* mu, const double* T, double* out,
                           hipStream_t s) {
   DGPYR_DISPATCH_ADJ(adjoint_n, c, mu, T, out, s)
+}
+
+static inline unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_rec_sample(const dgpyr_ctx& c, const double* U, double* out, hipStream_t s) {
+  if (c.nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rec_sample, dim3(blocks256(c.nrec)), dim3(256), 0, s, U, c.rec_elem,
+                     c.rec_phi, c.nrec, c.Np, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_inject(const dgpyr_ctx& c, double* Ub, const double* coef, hipStream_t s) {
+  if (c.nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rec_inject, dim3(1), dim3(256), 0, s, Ub, c.rec_elem, c.rec_phi, coef,
+                     c.nrec, c.Np);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_pre(const dgpyr_ctx& c, double* Rb, const double* Ub, double bs,
+                          hipStream_t s) {
+  const int64_t n = c.K * 4 * c.Np;
+  hipLaunchKernelGGL(k_adj_pre, dim3(blocks256(n)), dim3(256), 0, s, Rb, Ub, bs, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_post(const dgpyr_ctx& c, double* Ub, double* Rb, const double* ATRb,
+                           double dt, double as, hipStream_t s) {
+  const int64_t n = c.K * 4 * c.Np;
+  hipLaunchKernelGGL(k_adj_post, dim3(blocks256(n)), dim3(256), 0, s, Ub, Rb, ATRb, dt, as, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_kappa_grad(const dgpyr_ctx& c, double* grad, const double* Rb, const double* F,
+                             double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_kappa_grad, dim3(blocks256(c.K)), dim3(256), 0, s, grad, Rb, F,
+                     c.mesh.mat, c.K, c.Np, dt);
+  return hipGetLastError();
 }
 
 }  // namespace dgpyr

@@ -68,3 +68,68 @@ def test_adjoint_identity_full_size():
         gap, a, b = _identity_gap(s, K, 4, 7)
     log(f"[adjoint] identity full size: {a:.15e} vs {b:.15e} (gap {gap:.2e})")
     assert gap < 1e-13
+
+
+def _misfit_case(N, k1d, nsteps, nrec, seed):
+    from oracle import AcousticDG
+    from oracle.dg import wall_mode
+    xyz, e2v = hex_pyramid_mesh(k1d, seed=seed)
+    K = e2v.shape[0]
+    rng = np.random.default_rng(seed)
+    kap = rng.uniform(0.5, 2.0, K)
+    U0 = AcousticDG(xyz, e2v, N).project(wall_mode(1), xyz, e2v)
+    pts = rng.uniform(0.15, 0.85, (nrec, 3))
+    data = rng.normal(0.0, 0.1, (nsteps, nrec))
+    src = [dict(x=[0.4, 0.55, 0.45], f0=10.0)]
+    return xyz, e2v, kap, U0, pts, data, src
+
+
+def _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every, grad=True):
+    import torch
+
+    import paper_1502_07703_amd as dg
+    from paper_1502_07703_amd.adjoint import receiver_misfit
+    s = dg.Solver(xyz, e2v, N, alpha=0.0, sources=src)
+    s.set_receivers(pts)
+    U = s.pack(torch.from_numpy(U0).cuda())
+    k = torch.tensor(kap, dtype=torch.float64, requires_grad=grad)
+    J = receiver_misfit(k, s, U, torch.from_numpy(data).cuda(), dt, nsteps, every)
+    g = None
+    if grad:
+        J.backward()
+        g = k.grad.numpy().copy()
+    out = float(J.item())
+    s.close()
+    return out, g
+
+
+def test_misfit_gradient_matches_oracle_discrete_adjoint():
+    from oracle.adjoint import misfit_gradient, receiver_matrix
+    N, nsteps, dt = 2, 6, 0.02
+    xyz, e2v, kap, U0, pts, data, src = _misfit_case(N, 1, nsteps, 4, 3)
+    Rm = receiver_matrix(xyz, e2v, N, pts)
+    J_ref, g_ref, _ = misfit_gradient(xyz, e2v, N, kap, U0, dt, nsteps, Rm, data, sources=src)
+    J, g = _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every=4)
+    log(f"[adjoint] J {J:.15e} oracle {J_ref:.15e}")
+    assert abs(J - J_ref) <= 1e-12 * J_ref
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    log(f"[adjoint] kappa gradient rel err {err:.2e}")
+    assert err < 1e-10
+
+
+def test_misfit_gradient_central_differences():
+    """Gradient through the device adjoint against central differences of the
+    device misfit on seeded directions (162 pyramids, N = 3, 30 steps,
+    checkpoints every 10)."""
+    N, nsteps, dt = 3, 30, 0.01
+    xyz, e2v, kap, U0, pts, data, src = _misfit_case(N, 3, nsteps, 8, 5)
+    J, g = _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every=10)
+    rng = np.random.default_rng(9)
+    for i in range(3):
+        d = rng.normal(size=kap.size)
+        h = 1e-4
+        Jp, _ = _gpu_misfit(xyz, e2v, N, kap + h * d, U0, pts, data, src, dt, nsteps, 10, False)
+        Jm, _ = _gpu_misfit(xyz, e2v, N, kap - h * d, U0, pts, data, src, dt, nsteps, 10, False)
+        fd = (Jp - Jm) / (2 * h)
+        log(f"[adjoint] direction {i}: fd {fd:.12e} adjoint {g @ d:.12e}")
+        assert abs(fd - g @ d) <= 1e-6 * abs(fd)

@@ -166,6 +166,10 @@ def test_setup_errors_before_device(B):
     # calls on a missing context fail without touching a device
     L = B.lib()
     assert L.dgpyr_batch_step(None, None, None, 0, 1, None) != 0
+    assert L.dgpyr_set_kappa(None, None) != 0
+    assert L.dgpyr_set_receivers(None, 1, None) != 0
+    assert L.dgpyr_adjoint_step(None, None, None, None, 0.0, 0.1, None) != 0
+    assert L.dgpyr_adjoint_rhs(None, None, None, None) != 0
     assert L.dgpyr_batch_info(None, None, None) != 0
     assert L.dgpyr_set_groups(None, 1) != 0
     assert L.dgpyr_set_groups(None, 3) != 0
