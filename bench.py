@@ -275,6 +275,70 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(args):
+    """Adjoint form: gradient of a receiver misfit with respect to per-element
+    c^2 (kappa, rho = 1) through the discrete adjoint.  K1D^3 x 6 pyramids,
+    c^2 = 1 + 0.3 F(x) with F a seeded sum of Fourier modes (|k|_inf <= 4,
+    max |F| = 1) at element centroids, one Ricker source (f0 = 10), seeded
+    receivers, data recorded with c^2 = 1, checkpoints every few steps.
+    Prints one JSON line with the forward and gradient times."""
+    import torch
+
+    import paper_1502_07703_amd as dg
+    from paper_1502_07703_amd.adjoint import receiver_misfit
+    from synth import hex_pyramid_mesh
+    xyz, e2v = hex_pyramid_mesh(args.adjoint_k1d, seed=5)
+    K = e2v.shape[0]
+    N = args.N
+    rng = np.random.default_rng(5000)
+    cent = xyz[e2v].mean(axis=1)
+    F = np.zeros(K)
+    for _ in range(12):
+        k = rng.integers(-4, 5, 3)
+        F += rng.normal() * np.cos(2 * np.pi * (cent @ k) + rng.uniform(0, 2 * np.pi))
+    c2 = 1.0 + 0.3 * F / np.abs(F).max()
+    src = [dict(x=list(rng.uniform(0.3, 0.7, 3)), f0=10.0)]
+    rec = rng.uniform(0.1, 0.9, (args.adjoint_receivers, 3))
+    s = dg.Solver(xyz, e2v, N, alpha=0.0, sources=src)
+    s.set_receivers(rec)
+    U0 = s.empty_state().zero_()
+    dt = s.stable_dt(0.5) / np.sqrt(c2.max())
+    nsteps, every = args.adjoint_steps, args.adjoint_checkpoint
+    # data: the receiver traces of the true model c^2 = 1
+    with torch.no_grad():
+        s.set_kappa(np.ones(K))
+        U = U0.clone()
+        R = s.empty_state().zero_()
+        data = torch.empty((nsteps, s.nrec), dtype=torch.float64, device="cuda")
+        for n in range(nsteps):
+            s.step(U, R, dt, 1, t0=n * dt)
+            s.sample_receivers(U, data[n])
+    kap = torch.tensor(c2, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = receiver_misfit(kap, s, U0, data, dt, nsteps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = kap.grad.numpy()
+    Np = n_basis(N)
+    dof = 4 * Np * K
+    out = {"metric": "gradient of a receiver misfit w.r.t. per-element c^2 (discrete adjoint)",
+           "value": dof * 5 * nsteps / (t2 - t0) / 1e9, "unit": "GDOF·stages/s of forward run",
+           "n_gpus": 1, "steps": nsteps, "warmup": 0, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.adjoint_k1d}^3 x 6 = {K} pyramids, N={N}, c^2 = 1 + "
+                                  "0.3 F(x), central flux, walls, Ricker source, "
+                                  f"{s.nrec} receivers, {nsteps} steps, checkpoints every "
+                                  f"{every}", "nelems": K, "N": N, "dof": dof, "dt": dt},
+           "forward_s": t1 - t0, "gradient_s": t2 - t1, "misfit": float(J.item()),
+           "gradient_norm": float(np.linalg.norm(g)), "gradient_finite": bool(np.isfinite(g).all())}
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +368,12 @@ def main():
                     help="batched independent problems instead of the bench line")
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-k1d", default="4,24")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="adjoint-form gradient run instead of the bench line")
+    ap.add_argument("--adjoint-k1d", type=int, default=32)
+    ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--adjoint-checkpoint", type=int, default=20)
+    ap.add_argument("--adjoint-receivers", type=int, default=64)
     ap.add_argument("--study", action="store_true",
                     help="precision-form study instead of the bench line (see --study-*)")
     ap.add_argument("--study-k1d", type=int, default=64)
@@ -329,6 +399,9 @@ def main():
         return
     if args.batch:
         batch_bench(args)
+        return
+    if args.adjoint:
+        adjoint_bench(args)
         return
     N = args.N
     Np = n_basis(N)
