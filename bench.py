@@ -103,27 +103,42 @@ def recorded_traffic(kernel: str, workload: str):
     return None
 
 
-def wall_mode_values(P, m, t):
+def wall_mode_values(P, m, t, out=None, chunk=65536):
     """Exact wall eigenmode of the unit cube, (p, u, v, w) at points P (K, Nc, 3)
-    as a (K, 4, Nc) tensor: p = C cos(w t), u = sin(w t)/sqrt(3) grad-like terms,
-    C = cos(m pi x) cos(m pi y) cos(m pi z), w = sqrt(3) m pi."""
+    as a (K, 4, Nc) tensor: p = C cos(w t), u_k = sin(w t)/sqrt(3) times the
+    mode's k-th gradient factor, C = cos(m pi x) cos(m pi y) cos(m pi z),
+    w = sqrt(3) m pi.  Evaluated in element chunks to bound temporaries."""
     import torch
     k = m * np.pi
     om = np.sqrt(3.0) * k
-    x, y, z = P[..., 0], P[..., 1], P[..., 2]
-    cx, cy, cz = torch.cos(k * x), torch.cos(k * y), torch.cos(k * z)
-    sx, sy, sz = torch.sin(k * x), torch.sin(k * y), torch.sin(k * z)
     a = np.sin(om * t) / np.sqrt(3.0)
-    return torch.stack([cx * cy * cz * np.cos(om * t), a * sx * cy * cz, a * cx * sy * cz,
-                        a * cx * cy * sz], dim=1).contiguous()
+    K = P.shape[0]
+    if out is None:
+        out = torch.empty((K, 4, P.shape[1]), dtype=P.dtype, device=P.device)
+    for e0 in range(0, K, chunk):
+        x, y, z = (P[e0:e0 + chunk, :, d] for d in range(3))
+        cx, cy, cz = torch.cos(k * x), torch.cos(k * y), torch.cos(k * z)
+        o = out[e0:e0 + chunk]
+        o[:, 0] = cx * cy * cz * np.cos(om * t)
+        o[:, 1] = a * torch.sin(k * x) * cy * cz
+        o[:, 2] = a * cx * torch.sin(k * y) * cz
+        o[:, 3] = a * cx * cy * torch.sin(k * z)
+    return out
 
 
-def l2_norm(solver, U, P, wJ, f=None):
-    """sqrt(sum_q w_q J_q |U(x_q) - f_q|^2) over all fields on the volume rule."""
+def l2_norm(solver, U, P, wJ, mode=None, chunk=65536):
+    """sqrt(sum_q w_q J_q |U(x_q) - f_q|^2) over all fields on the volume rule;
+    f is the wall mode (m, t) = ``mode`` or zero."""
     import torch
     vals = solver.evaluate(U)
-    d = vals if f is None else vals - f
-    return float(torch.sqrt((wJ[:, None, :] * d * d).sum()).item())
+    tot = 0.0
+    for e0 in range(0, vals.shape[0], chunk):
+        d = vals[e0:e0 + chunk]
+        if mode is not None:
+            d = d - wall_mode_values(P[e0:e0 + chunk], mode[0], mode[1])
+        tot += float((wJ[e0:e0 + chunk, None, :] * d * d).sum().item())
+    del vals
+    return float(np.sqrt(tot))
 
 
 def cpu_baseline(xyz, e2v, N, U, nsample, reps=3):
@@ -196,7 +211,7 @@ def precision_study(args):
                     wall, names, ms, cnt = timed_steps(dg, s, U, R, 0.0, dt, args.study_steps,
                                                        stream)
                     T_end = args.study_steps * dt
-                    e = l2_norm(s, U, P, wJ, wall_mode_values(P, m, T_end))
+                    e = l2_norm(s, U, P, wJ, (m, T_end))
                     entry = {"gdof_stages_per_s": 4 * Np * K * 5 * args.study_steps / wall / 1e9,
                              "l2_error_vs_mode": e,
                              "kernels_ms": {nm: ms[i] / max(cnt[i], 1) for i, nm in enumerate(names)}}
@@ -356,6 +371,9 @@ def main():
     ap.add_argument("--groups", type=int, default=0,
                     help="4-element groups per wave of the fused matrix-core kernels "
                          "(0 = library default)")
+    ap.add_argument("--lds-operators", type=int, default=-1,
+                    help="1: stage operator tiles in LDS per workgroup, 0: do not, "
+                         "-1: library default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 256 MiB buffer 3 times (a plain copy "
                          "of known size for scaling HBM counters)")
@@ -409,7 +427,8 @@ def main():
     K = e2v.shape[0]
     solver = dg.Solver(xyz, e2v, N, precision=args.precision,
                        reference_kernels=args.reference_kernels, unfused=args.unfused,
-                       sum_factorized=args.sum_factorized, groups_per_wave=args.groups)
+                       sum_factorized=args.sum_factorized, groups_per_wave=args.groups,
+                       lds_operators=None if args.lds_operators < 0 else bool(args.lds_operators))
     # initial data: the unit-cube wall eigenmode (mode m), L2-projected on the device
     P, wJ = solver.volume_points()
     U0 = solver.project(wall_mode_values(P, args.mode, 0.0))
@@ -494,8 +513,7 @@ def main():
     # Error of the run against the exact mode at the final time, and the
     # precision forms on the same workload, initial data and step count.
     T_end = (args.warmup + args.steps) * dt
-    exact = wall_mode_values(P, args.mode, T_end)
-    e_main = l2_norm(solver, U, P, wJ, exact)
+    e_main = l2_norm(solver, U, P, wJ, (args.mode, T_end))
     out["l2_error_vs_mode"] = {"mode": args.mode, "t": T_end, "value": e_main}
     if (not args.no_forms and args.precision == "fp64" and not args.reference_kernels
             and not args.sum_factorized and not args.unfused):
@@ -507,7 +525,7 @@ def main():
                 sf.step(Uf, Rf, dt, args.warmup)
                 wf, nf, msf, cf = timed_steps(dg, sf, Uf, Rf, args.warmup * dt, dt, args.steps,
                                               stream)
-                e_f = l2_norm(sf, Uf, P, wJ, exact)
+                e_f = l2_norm(sf, Uf, P, wJ, (args.mode, T_end))
                 d_f = l2_norm(sf, Uf - U, P, wJ)
                 vf = 4 * Np * K * stages / wf / 1e9
                 forms[form] = {

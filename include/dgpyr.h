@@ -287,6 +287,15 @@ void dgpyr_batch_destroy(dgpyr_batch* b);
 dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,
                                   int64_t* needed);
 
+/* Operator staging of the fused matrix-core stage kernel: with enable != 0
+ * each workgroup copies the derivative, projection and lift fragments of a
+ * tile into LDS once and its four waves share them (one 4-element group per
+ * wave); used where the tile fits in 64 KiB of LDS (FP64 N <= 5, FP32
+ * N <= 6), elsewhere the default kernel runs.  Same results to rounding.
+ * Default: on for the FP32 form, off for FP64 (measured).  Takes effect at
+ * the next launch. */
+dgpyr_status dgpyr_set_operator_staging(dgpyr_ctx* ctx, int32_t enable);
+
 /* Host-only location of the mesh's point sources (what dgpyr_setup does
  * before touching the device): elem[s] (optional, [nsources]) receives the
  * containing element and abc (optional, [nsources][3]) the collapsed

@@ -105,7 +105,8 @@ class Solver:
 
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
                  precision="fp64", reference_kernels=False, unfused=False,
-                 sum_factorized=False, groups_per_wave=0, sources=None, stream=None):
+                 sum_factorized=False, groups_per_wave=0, sources=None, lds_operators=None,
+                 stream=None):
         L = B.lib()
         self._host = _HostMesh(xyz, e2v, rho, kappa, bc, sources)
         mesh = self._host.struct
@@ -123,6 +124,13 @@ class Solver:
         self.state_len, self.canon_len = info.state_len, info.canon_len
         if groups_per_wave:
             self.set_groups(groups_per_wave)
+        if lds_operators is not None:
+            self.set_operator_staging(lds_operators)
+
+    def set_operator_staging(self, enable: bool):
+        """Stage operator tiles in LDS per workgroup in the fused stage kernel."""
+        B.check(B.lib().dgpyr_set_operator_staging(self._h, 1 if enable else 0),
+                "dgpyr_set_operator_staging")
 
     # -- state helpers -----------------------------------------------------------
     def empty_state(self):

@@ -445,6 +445,10 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   c->unfused = (opts->flags & DGPYR_FLAG_UNFUSED) != 0;
   c->sum_factorized = (opts->flags & DGPYR_FLAG_SUM_FACTORIZED) != 0;
   c->mfma_groups = default_groups(N, opts->precision);
+  // Operator staging in LDS: measured at 384000 pyramids, N = 4, it speeds the
+  // FP32 stage up (2.47 -> 2.29 ms) but slows the FP64 one (3.09 -> 3.44 ms;
+  // N = 5 at 196608 pyramids: 3.84 -> 4.64 ms), so it is on for FP32 only.
+  c->lds_operators = opts->precision == DGPYR_FP32_MFMA;
 
   std::vector<int> perm((size_t)10 * ops.Nfq);
   for (int o = 0; o < 8; ++o) dgpyr::quad_perm(N, o, &perm[(size_t)o * ops.Nfq]);
@@ -651,6 +655,12 @@ dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* c, const double* lam, double* out, voi
   if (e == hipSuccess) e = dgpyr::launch_trace_mfma(*c, c->adj_mu, c->T, s);
   if (e == hipSuccess) e = dgpyr::launch_adjoint(*c, c->adj_mu, c->T, out, s);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "adjoint launch");
+}
+
+dgpyr_status dgpyr_set_operator_staging(dgpyr_ctx* c, int32_t enable) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  c->lds_operators = enable != 0;
+  return DGPYR_OK;
 }
 
 dgpyr_status dgpyr_set_groups(dgpyr_ctx* c, int32_t groups) {

@@ -136,6 +136,7 @@ struct dgpyr_ctx {
   bool unfused = false;            // separate matrix-core volume and surface launches
   bool sum_factorized = false;     // FP64 sum-factorised kernels
   int mfma_groups = 1;             // 4-element groups per wave (fused matrix core)
+  bool lds_operators = false;      // stage operator tiles in LDS per workgroup
   dgpyr::SfOps sf{};
   dgpyr::Bf16Ops bf{};
   const double* xc = nullptr;      // [N+1] Gauss-Jacobi(2,0) nodes in c

@@ -455,6 +455,173 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
   }
 }
 
+// Fused stage with the operator fragments of each tile staged in LDS once per
+// workgroup: the four waves share every fragment instead of each streaming it
+// from L2 (the vector-memory address unit was the stage kernel's limiter).
+// Per volume tile the workgroup copies the derivative and projection
+// fragments of that tile (16 bytes per thread and load) between two
+// barriers, then every wave reads its B operands from LDS; the surface tiles
+// stage the lift fragments the same way.  One 4-element group per wave.
+template <int N, int FORM>
+struct StagedDims {
+  using TT = Tiles<N>;
+  using TV = typename Mma<FORM>::T;
+  static constexpr int KP = Pack<TV>::KP;
+  static constexpr int NCHP = (TT::NCH + KP - 1) / KP;
+  static constexpr int NITP = (TT::NIT + KP - 1) / KP;
+  static constexpr int DPACKS = NCHP * 64;   // packs of one derivative operator per tile
+  static constexpr int PPACKS = 4 * NITP * 64;  // packs of a projection / lift tile
+  static constexpr int PACKS = 3 * DPACKS + PPACKS;
+  static constexpr int BYTES = PACKS * 16;
+  // fits one workgroup's LDS next to the vertex and transpose tiles, under 64 KiB
+  static constexpr bool fits = BYTES + kEB * 16 * 8 + kWaves * 16 * 17 * 8 <= 65536;
+};
+
+template <int N, int FORM, int MODE>
+__global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, 1>::value)) void k_stage_staged(
+    const double* __restrict__ U, const double* __restrict__ T, FragOps fo, DevOps ops,
+    DevMesh mesh, double* out, double* R, double ra, double rb, double dt) {
+  using TT = Tiles<N>;
+  using M = Mma<FORM>;
+  using TV = typename M::T;
+  using SD = StagedDims<N, FORM>;
+  constexpr int KP = SD::KP, NCHP = SD::NCHP, NITP = SD::NITP;
+  using PV = typename Pack<TV>::V;
+  __shared__ double sX[kEB][16];
+  __shared__ TV sQ[kWaves][16][17];
+  __shared__ PV sB[SD::PACKS];  // [Dr | Ds | Dt][NCHP][64], then [4][NITP][64]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t eb0 = (int64_t)blockIdx.x * kEB;
+  for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
+    const int64_t e = eb0 + x / 16;
+    sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
+  }
+  const int64_t ew0 = eb0 + wv * kEW;
+  TV afr[TT::NCH];
+  load_u_frags<N, FORM>(U, ew0, mesh.K, lane, afr);
+
+  const PV* DrF = reinterpret_cast<const PV*>(fo.DrF);
+  const PV* DsF = reinterpret_cast<const PV*>(fo.DsF);
+  const PV* DtF = reinterpret_cast<const PV*>(fo.DtF);
+  const PV* VF = reinterpret_cast<const PV*>(fo.VF);
+  const PV* LfF = reinterpret_cast<const PV*>(fo.LfF);
+  const int de = lane >> 4, dq = lane & 15;
+  const int row = lane & 15, kq = lane >> 4;
+  const int64_t e = ew0 + de;
+  const double* xv = sX[wv * kEW + de];
+  typename M::Acc z[TT::NIT];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) z[u] = M::zero();
+
+  // volume (Algorithm 1)
+  for (int t = 0; t < TT::NTC; ++t) {
+    __syncthreads();  // previous tile's readers are done with sB
+    for (int x = threadIdx.x; x < SD::PACKS; x += kBlock) {
+      const int op = x / SD::DPACKS;
+      const int r = x - op * SD::DPACKS;
+      sB[x] = op == 0   ? DrF[(size_t)t * SD::DPACKS + r]
+              : op == 1 ? DsF[(size_t)t * SD::DPACKS + r]
+              : op == 2 ? DtF[(size_t)t * SD::DPACKS + r]
+                        : VF[(size_t)t * SD::PPACKS + (x - 3 * SD::DPACKS)];
+    }
+    __syncthreads();
+    typename M::Acc yr = M::zero(), ys = M::zero(), yt = M::zero();
+    PV pr, ps, pt;
+#pragma unroll
+    for (int c = 0; c < TT::NCH; ++c) {
+      if (c % KP == 0) {
+        const int o = (c / KP) * 64 + lane;
+        pr = sB[o];
+        ps = sB[SD::DPACKS + o];
+        pt = sB[2 * SD::DPACKS + o];
+      }
+      yr = M::mma(afr[c], pr[c % KP], yr);
+      ys = M::mma(afr[c], ps[c % KP], ys);
+      yt = M::mma(afr[c], pt[c % KP], yt);
+    }
+    const int q = 16 * t + dq;
+    double Q[4] = {0.0, 0.0, 0.0, 0.0};
+    if (q < TT::Nc) {
+      const int pm = q % TT::Nfq;
+      double adj[9], J;
+      pyr_metric(xv, ops.xg[pm % TT::n1], ops.xg[pm / TT::n1], adj, &J);
+      const double w = ops.wv[q];
+      double dr[4], ds[4], dtt[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        dr[v] = (double)yr[v];
+        ds[v] = (double)ys[v];
+        dtt[v] = (double)yt[v];
+      }
+      double qp = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        qp += adj[k] * dr[1 + k] + adj[3 + k] * ds[1 + k] + adj[6 + k] * dtt[1 + k];
+      Q[0] = w * qp;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        Q[1 + k] = w * (adj[k] * dr[0] + adj[3 + k] * ds[0] + adj[6 + k] * dtt[0]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sQ[wv][M::row(de, v)][dq] = (TV)Q[v];
+    wave_lds_sync();
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const TV a = sQ[wv][row][4 * c2 + kq];
+      PV pv;
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) {
+        if (u % KP == 0) pv = sB[3 * SD::DPACKS + (c2 * NITP + u / KP) * 64 + lane];
+        z[u] = M::mma(a, pv[u % KP], z[u]);
+      }
+    }
+    wave_lds_sync();
+  }
+
+  // surface (Algorithm 2)
+  for (int t = 0; t < TT::NTF; ++t) {
+    const int q = 16 * t + dq;
+    double F[4] = {0.0, 0.0, 0.0, 0.0};
+    if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
+    __syncthreads();
+    for (int x = threadIdx.x; x < SD::PPACKS; x += kBlock) sB[x] = LfF[(size_t)t * SD::PPACKS + x];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sQ[wv][M::row(de, v)][dq] = (TV)F[v];
+    wave_lds_sync();
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const TV a = sQ[wv][row][4 * c2 + kq];
+      PV pv;
+#pragma unroll
+      for (int u = 0; u < TT::NIT; ++u) {
+        if (u % KP == 0) pv = sB[(c2 * NITP + u / KP) * 64 + lane];
+        z[u] = M::mma(a, pv[u % KP], z[u]);
+      }
+    }
+    wave_lds_sync();
+  }
+
+  // inverse mass, material, RK stage (Algorithm 3)
+  if (e >= mesh.K) return;
+  double jc[4];
+  pyr_jac_coeffs(xv, jc);
+  const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
+  const double dte = dt * mesh.mat[e * 4 + 3];
+#pragma unroll
+  for (int u = 0; u < TT::NIT; ++u) {
+    const int i = 16 * u + dq;
+    if (i >= TT::Np) continue;
+    const double minv = 1.0 / (pyr_jac_eval(jc, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double acc = (double)z[u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);
+      finish_coeff<MODE>(acc, minv, v == 0 ? kap : irho, out, R, (e * 4 + v) * TT::Np + i, ra,
+                         rb, dte);
+    }
+  }
+}
+
 // Element groups per wave of the fused stage (1 or 2, set per context) and of
 // the trace (2 up to N = 5: measured at N = 4, 0.74 ms against 0.82 ms for one
 // group; above, two groups need more registers than four waves per SIMD leave).
@@ -474,10 +641,31 @@ hipError_t stage_mfma_n(const dgpyr_ctx& c, int mode, const double* U, const dou
   return hipGetLastError();
 }
 
+template <int N, int FORM>
+hipError_t stage_staged_n(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                          double* out, double* R, double ra, double rb, double dt, hipStream_t s) {
+  const int64_t nb = (c.K + kEB - 1) / kEB;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stage_staged<N, FORM, 0>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T,
+                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+  else
+    hipLaunchKernelGGL((k_stage_staged<N, FORM, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, U, T,
+                       c.frag, c.ops, c.mesh, out, R, ra, rb, dt);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t stage_mfma_dispatch(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                                double* out, double* R, double ra, double rb, double dt,
                                hipStream_t s) {
+  if (c.lds_operators) {
+    if (c.precision == DGPYR_FP32_MFMA) {
+      if constexpr (StagedDims<N, 1>::fits)
+        return stage_staged_n<N, 1>(c, mode, U, T, out, R, ra, rb, dt, s);
+    } else if constexpr (StagedDims<N, 0>::fits) {
+      return stage_staged_n<N, 0>(c, mode, U, T, out, R, ra, rb, dt, s);
+    }
+  }
   const bool two = mfma_groups(c) == 2;
   if (c.precision == DGPYR_FP32_MFMA)
     return two ? stage_mfma_n<N, 1, 2>(c, mode, U, T, out, R, ra, rb, dt, s)

@@ -229,3 +229,33 @@ def test_rhs_split_bf16_form(N):
     log(f"[bf16] N={N} rel err per field {err}")
     assert np.all(err < 2e-4), err
     assert np.any(err > 1e-10), "split-BF16 form gave FP64-accurate results: wrong kernels?"
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 4, 5, 6])
+def test_rhs_parity_operator_staging(N):
+    """Operator tiles staged in LDS per workgroup (FP64 up to N = 5, FP32 up to
+    N = 6; above that the default kernel runs) on the cfg1 mesh and a ragged
+    subset, and one LSRK step."""
+    import torch
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    for sub in (48, 29):
+        e = e2v[:sub]
+        K = e.shape[0]
+        rho, kap = random_materials(K, seed=N)
+        U = random_state(K, N, seed=60 + N)
+        o = AcousticDG(xyz, e, N, rho=rho, kappa=kap)
+        ref = o.rhs(U)
+        with _solver(xyz, e, N, rho=rho, kappa=kap, lds_operators=True) as s:
+            got = gpu_rhs(s, U)
+        assert np.all(rel_err_per_field(got, ref) < TOL), (sub, rel_err_per_field(got, ref))
+        with _solver(xyz, e, N, rho=rho, kappa=kap, precision="fp32_mfma", lds_operators=True) as s:
+            got = gpu_rhs(s, U)
+        assert np.all(rel_err_per_field(got, ref) < 2e-5), sub
+    dt = 1e-3
+    ref, _ = lsrk_run(o.rhs, U, dt, 2)
+    with _solver(xyz, e, N, rho=rho, kappa=kap, lds_operators=True) as s:
+        Ud = s.pack(torch.from_numpy(U).cuda())
+        R = s.empty_state().zero_()
+        s.step(Ud, R, dt, 2)
+        got = s.unpack(Ud).cpu().numpy()
+    assert np.all(rel_err_per_field(got, ref) < 1e-11)
