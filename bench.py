@@ -371,6 +371,8 @@ def main():
     ap.add_argument("--groups", type=int, default=0,
                     help="4-element groups per wave of the fused matrix-core kernels "
                          "(0 = library default)")
+    ap.add_argument("--trace-groups", type=int, default=0,
+                    help="4-element groups per wave of the trace kernel (0 = library default)")
     ap.add_argument("--lds-operators", type=int, default=-1,
                     help="1: stage operator tiles in LDS per workgroup, 0: do not, "
                          "-1: library default")
@@ -428,7 +430,8 @@ def main():
     solver = dg.Solver(xyz, e2v, N, precision=args.precision,
                        reference_kernels=args.reference_kernels, unfused=args.unfused,
                        sum_factorized=args.sum_factorized, groups_per_wave=args.groups,
-                       lds_operators=None if args.lds_operators < 0 else bool(args.lds_operators))
+                       lds_operators=None if args.lds_operators < 0 else bool(args.lds_operators),
+                       trace_groups=args.trace_groups)
     # initial data: the unit-cube wall eigenmode (mode m), L2-projected on the device
     P, wJ = solver.volume_points()
     U0 = solver.project(wall_mode_values(P, args.mode, 0.0))

@@ -287,6 +287,11 @@ void dgpyr_batch_destroy(dgpyr_batch* b);
 dgpyr_status dgpyr_host_reference(int32_t N, int32_t which, double* out, int64_t len,
                                   int64_t* needed);
 
+/* Work shape of the matrix-core trace kernel: 4-element groups per wave
+ * (1, 2 or 4; 0 = the library's choice for N).  Same results for every
+ * choice.  Takes effect at the next launch. */
+dgpyr_status dgpyr_set_trace_groups(dgpyr_ctx* ctx, int32_t groups);
+
 /* Operator staging of the fused matrix-core stage kernel: with enable != 0
  * each workgroup copies the derivative, projection and lift fragments of a
  * tile into LDS once and its four waves share them (one 4-element group per

@@ -106,7 +106,7 @@ class Solver:
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
                  precision="fp64", reference_kernels=False, unfused=False,
                  sum_factorized=False, groups_per_wave=0, sources=None, lds_operators=None,
-                 stream=None):
+                 trace_groups=0, stream=None):
         L = B.lib()
         self._host = _HostMesh(xyz, e2v, rho, kappa, bc, sources)
         mesh = self._host.struct
@@ -126,6 +126,12 @@ class Solver:
             self.set_groups(groups_per_wave)
         if lds_operators is not None:
             self.set_operator_staging(lds_operators)
+        if trace_groups:
+            self.set_trace_groups(trace_groups)
+
+    def set_trace_groups(self, groups: int):
+        """Element groups per wave of the trace kernel (0 = default)."""
+        B.check(B.lib().dgpyr_set_trace_groups(self._h, int(groups)), "dgpyr_set_trace_groups")
 
     def set_operator_staging(self, enable: bool):
         """Stage operator tiles in LDS per workgroup in the fused stage kernel."""

@@ -26,7 +26,7 @@ EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
     "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_set_kappa",
     "dgpyr_set_receivers", "dgpyr_receivers_sample", "dgpyr_receivers_inject",
-    "dgpyr_adjoint_step", "dgpyr_set_operator_staging", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
+    "dgpyr_adjoint_step", "dgpyr_set_operator_staging", "dgpyr_set_trace_groups", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
     "dgpyr_host_mesh", "dgpyr_host_sources", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
     "dgpyr_batch_setup", "dgpyr_batch_info", "dgpyr_batch_problem", "dgpyr_batch_group",
@@ -114,6 +114,8 @@ def lib():
     L.dgpyr_adjoint_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double,
                                      c_void_p]
     L.dgpyr_adjoint_step.restype = c_int32
+    L.dgpyr_set_trace_groups.argtypes = [c_void_p, c_int32]
+    L.dgpyr_set_trace_groups.restype = c_int32
     L.dgpyr_set_operator_staging.argtypes = [c_void_p, c_int32]
     L.dgpyr_set_operator_staging.restype = c_int32
     L.dgpyr_set_groups.argtypes = [c_void_p, c_int32]

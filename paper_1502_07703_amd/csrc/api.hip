@@ -657,6 +657,14 @@ dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* c, const double* lam, double* out, voi
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "adjoint launch");
 }
 
+dgpyr_status dgpyr_set_trace_groups(dgpyr_ctx* c, int32_t groups) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (groups != 0 && groups != 1 && groups != 2 && groups != 4)
+    return fail(DGPYR_E_ARG, "trace groups must be 0, 1, 2 or 4");
+  c->trace_groups = groups;
+  return DGPYR_OK;
+}
+
 dgpyr_status dgpyr_set_operator_staging(dgpyr_ctx* c, int32_t enable) {
   if (dgpyr_status s = check_ctx(c)) return s;
   c->lds_operators = enable != 0;

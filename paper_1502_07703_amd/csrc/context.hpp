@@ -137,6 +137,7 @@ struct dgpyr_ctx {
   bool sum_factorized = false;     // FP64 sum-factorised kernels
   int mfma_groups = 1;             // 4-element groups per wave (fused matrix core)
   bool lds_operators = false;      // stage operator tiles in LDS per workgroup
+  int trace_groups = 0;            // 4-element groups per wave of the trace (0: by N)
   dgpyr::SfOps sf{};
   dgpyr::Bf16Ops bf{};
   const double* xc = nullptr;      // [N+1] Gauss-Jacobi(2,0) nodes in c

@@ -281,12 +281,13 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 // Waves per SIMD the fused stage kernel is compiled for: the largest count
 // whose register budget (512 / waves) holds the kernel without spilling
 // (checked on the gfx950 build: FP64 N = 4, one group: 150 registers for three
-// waves against 200 when unconstrained).
+// waves against 200 when unconstrained; FP64 N = 6: 236 for two waves against
+// 312).
 template <int N, int FORM, int G>
 struct StageWaves {
   static constexpr int value =
       G == 2 ? (FORM == 0 ? (N <= 4 ? 2 : 1) : (N <= 6 ? 2 : 1))
-             : (FORM == 0 ? (N <= 4 ? 3 : N == 5 ? 2 : 1) : (N <= 6 ? 3 : 2));
+             : (FORM == 0 ? (N <= 4 ? 3 : N <= 6 ? 2 : 1) : (N <= 6 ? 3 : 2));
 };
 
 template <int N, int FORM, int MODE, int G>
@@ -623,10 +624,14 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, 1>::value)) void k_sta
 }
 
 // Element groups per wave of the fused stage (1 or 2, set per context) and of
-// the trace (2 up to N = 5: measured at N = 4, 0.74 ms against 0.82 ms for one
-// group; above, two groups need more registers than four waves per SIMD leave).
+// the trace (default by N; measured at 384000 pyramids, N = 4: 0.82 ms with
+// one group, 0.74 ms with two, 0.62 ms with four; four groups at N = 5 and
+// two at N >= 6 need more registers than leave several waves per SIMD).
 inline int mfma_groups(const dgpyr_ctx& c) { return c.mfma_groups == 2 ? 2 : 1; }
-inline int trace_groups(const dgpyr_ctx& c) { return c.N <= 5 ? 2 : 1; }
+inline int trace_groups(const dgpyr_ctx& c) {
+  if (c.trace_groups == 1 || c.trace_groups == 2 || c.trace_groups == 4) return c.trace_groups;
+  return c.N <= 4 ? 4 : c.N == 5 ? 2 : 1;
+}
 
 template <int N, int FORM, int G>
 hipError_t stage_mfma_n(const dgpyr_ctx& c, int mode, const double* U, const double* T, double* out,
@@ -684,7 +689,11 @@ hipError_t trace_mfma_g(const dgpyr_ctx& c, const double* U, double* T, hipStrea
 
 template <int N>
 hipError_t trace_mfma_n(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s) {
-  return trace_groups(c) == 2 ? trace_mfma_g<N, 2>(c, U, T, s) : trace_mfma_g<N, 1>(c, U, T, s);
+  switch (trace_groups(c)) {
+    case 4: return trace_mfma_g<N, 4>(c, U, T, s);
+    case 2: return trace_mfma_g<N, 2>(c, U, T, s);
+    default: return trace_mfma_g<N, 1>(c, U, T, s);
+  }
 }
 
 template <int N, int FORM>

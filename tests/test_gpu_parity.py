@@ -259,3 +259,22 @@ def test_rhs_parity_operator_staging(N):
         s.step(Ud, R, dt, 2)
         got = s.unpack(Ud).cpu().numpy()
     assert np.all(rel_err_per_field(got, ref) < 1e-11)
+
+
+@pytest.mark.parametrize("N", [0, 2, 4, 5, 6])
+def test_rhs_parity_trace_groups(N):
+    """The trace kernel with 1, 2 and 4 element groups per wave (cfg1 mesh and
+    a ragged subset): identical results."""
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    for sub in (48, 13):
+        e = e2v[:sub]
+        K = e.shape[0]
+        U = random_state(K, N, seed=80 + N)
+        ref = AcousticDG(xyz, e, N).rhs(U)
+        outs = []
+        for tg in (1, 2, 4):
+            with _solver(xyz, e, N, trace_groups=tg) as s:
+                got = gpu_rhs(s, U)
+            assert np.all(rel_err_per_field(got, ref) < TOL), (sub, tg)
+            outs.append(got)
+        assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
