@@ -15,6 +15,9 @@ It is written to be plain, slow and checkable against the paper by eye:
                   with every element mass matrix assembled by quadrature and
                   inverted through an LU factorisation, plus projection, L2
                   error and energy.
+* ``advection``-- the semi-discrete advection DG right-hand side of
+                  Section 4.1 (upwind / central flux, periodic cubes).
+* ``adjoint``  -- the discrete adjoint of the acoustic LSRK stepping.
 * ``lsrk``     -- the low-storage RK(5,4) time stepper (Section 4.1,
                   Algorithm 3), coefficients of Carpenter and Kennedy.
 

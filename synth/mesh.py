@@ -137,3 +137,18 @@ def warped_pyramid(gamma: float):
     xyz[:4, 0] += 0.1 * gamma * np.array([0.0, 1.0, 0.5, -0.5])
     xyz[4, :2] += 0.3 * gamma
     return xyz, e2v
+
+
+def periodic_pair_ids(xyz, lo: float = -1.0, hi: float = 1.0, tol: float = 1e-9):
+    """Vertex identities of the periodic cube [lo, hi]^3: vertices whose
+    coordinates agree modulo hi - lo share one id (the lowest vertex index
+    among them); every other vertex keeps its own index.  Meshes from
+    ``hex_pyramid_mesh`` keep their boundary vertices on the regular grid, so
+    opposite boundary faces then have equal vertex-id sets."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    L = hi - lo
+    w = np.mod(xyz - lo, L)
+    w[w >= L - tol] = 0.0
+    key = np.round(w / (tol * 10.0)).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    return first[inv.ravel()].astype(np.int64)
