@@ -290,6 +290,88 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def adv_work(name: str, N: int):
+    """Algorithmic flops and HBM bytes per element for one launch of an
+    advection kernel (one field): trace V^f u; stage [Dr;Ds;Dt] u, pointwise
+    beta . adj metric, V^T (W .), face term, LIFT, inverse mass, LSRK."""
+    Np, n1 = n_basis(N), N + 1
+    Nc, Nfc, Nab = n1 ** 3, 5 * n1 ** 2, n1 ** 2
+    if name == "trace":
+        return 2 * Nfc * Np, 8 * Np + 8 * Nab
+    if name == "stage":
+        return (8 * Nc * Np + 2 * Nfc * Np + 10 * Nc + 8 * Nfc + 6 * Np,
+                32 * Np + 8 * Nab + 152)
+    raise KeyError(name)
+
+
+def advection_bench(args):
+    """Second workload (Section 4.1): u_t + div(beta u) = 0, beta = (1, 0.3,
+    -0.5), upwind flux, on the periodic bi-unit cube cut into K1D^3 x 6
+    perturbed pyramids; initial data sin(pi (x + y)) projected on the device;
+    CFL 0.5 time steps.  One JSON line per N with throughput, kernel times,
+    the stage kernel's roofline and the L2 error against the transported
+    wave."""
+    import torch
+
+    import paper_1502_07703_amd as dg
+    from synth import hex_pyramid_mesh, periodic_pair_ids
+    beta = np.array([1.0, 0.3, -0.5])
+    kv = np.pi * np.array([1.0, 1.0, 0.0])
+    xyz, e2v = hex_pyramid_mesh(args.advection_k1d, seed=2, lo=-1.0, hi=1.0)
+    pid = periodic_pair_ids(xyz)
+    K = e2v.shape[0]
+    stream = torch.cuda.current_stream()
+    for N in [int(x) for x in args.advection_N.split(",")]:
+        Np = n_basis(N)
+        print(f"[advection] N={N} K={K}", file=sys.stderr, flush=True)
+        with dg.Advection(xyz, e2v, N, beta, alpha=1.0, pair_ids=pid) as s:
+            P, wJ = s.volume_points()
+            kt = torch.from_numpy(kv).cuda()
+            U = s.project(torch.sin(P @ kt).unsqueeze(1).contiguous())
+            R = s.empty_state().zero_()
+            dt = s.stable_dt(0.5)
+            s.step(U, R, dt, args.warmup)
+            wall, names, ms, cnt = timed_steps(dg, s, U, R, args.warmup * dt, dt,
+                                               args.advection_steps, stream)
+            T = (args.warmup + args.advection_steps) * dt
+            f = s.evaluate(U)[:, 0]
+            exact = torch.sin((P - torch.from_numpy(beta * T).cuda()) @ kt)
+            err = float(torch.sqrt((wJ * (f - exact) ** 2).sum()))
+            del P, wJ, f, exact
+        kernels = {}
+        for i, nm in enumerate(names):
+            avg = ms[i] / max(cnt[i], 1)
+            F, Bb = adv_work(nm, N)
+            kernels[nm] = {"avg_ms": avg, "launches": int(cnt[i]),
+                           "tflops": F * K / (avg * 1e-3) / 1e12,
+                           "gbs": Bb * K / (avg * 1e-3) / 1e9}
+        F, Bb = adv_work("stage", N)
+        t = kernels["stage"]["avg_ms"] * 1e-3
+        mf = F / (PEAK_FP64_TFLOPS * 1e12) >= Bb / (PEAK_HBM_GBS * 1e9)
+        if mf:
+            roof = {"bound": "mfma", "achieved": F * K / t / 1e12, "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": Bb * K / t / 1e9, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        stages = 5 * args.advection_steps
+        out = {"metric": "GDOF·stages/s, advection", "value": Np * K * stages / wall / 1e9,
+               "unit": "GDOF·stages/s", "n_gpus": 1, "steps": args.advection_steps,
+               "warmup": args.warmup, "ms_per_step": wall / args.advection_steps * 1e3,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"periodic bi-unit cube, {args.advection_k1d}^3 perturbed "
+                                      f"hexes x 6 = {K} pyramids, N={N}, 1 field, upwind flux, "
+                                      "beta = (1, 0.3, -0.5), LSRK(5,4)",
+                          "nelems": K, "N": N, "Np": Np, "dof": K * Np, "dt": dt,
+                          "l2_error_vs_transported_wave": err},
+               "kernels": kernels, "roofline": roof}
+        print(json.dumps(out), flush=True)
+        torch.cuda.empty_cache()
+
+
 def adjoint_bench(args):
     """Adjoint form: gradient of a receiver misfit with respect to per-element
     c^2 (kappa, rho = 1) through the discrete adjoint.  K1D^3 x 6 pyramids,
@@ -394,6 +476,11 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--adjoint-checkpoint", type=int, default=20)
     ap.add_argument("--adjoint-receivers", type=int, default=64)
+    ap.add_argument("--advection", action="store_true",
+                    help="advection workload (Section 4.1) instead of the bench line")
+    ap.add_argument("--advection-k1d", type=int, default=64)
+    ap.add_argument("--advection-N", default="1,2,3,4,5,6")
+    ap.add_argument("--advection-steps", type=int, default=20)
     ap.add_argument("--study", action="store_true",
                     help="precision-form study instead of the bench line (see --study-*)")
     ap.add_argument("--study-k1d", type=int, default=64)
@@ -422,6 +509,9 @@ def main():
         return
     if args.adjoint:
         adjoint_bench(args)
+        return
+    if args.advection:
+        advection_bench(args)
         return
     N = args.N
     Np = n_basis(N)

@@ -107,14 +107,15 @@ typedef struct {
   int32_t Nfc;             /* surface cubature points 5 (N+1)^2                    */
   int64_t nelems;          /* K                                                    */
   int64_t state_len;       /* doubles in one state array (U, R or dU/dt)           */
-  int64_t canon_len;       /* doubles in the canonical array, K * 4 * Np           */
+  int64_t canon_len;       /* doubles in the canonical array, K * nfields * Np     */
   double inv_length_max;   /* max over elements of c_K |dK| / |K|                  */
   int32_t hex_groups;      /* 1 if elements come in groups of 6 sharing an apex    */
   int32_t precision;       /* precision form built                                 */
   int64_t device_bytes;    /* device memory held by the context                    */
   int32_t groups_per_wave; /* 4-element groups per wave of the fused matrix-core
                               kernels (dgpyr_set_groups)                         */
-  int32_t reserved;        /* 0                                                    */
+  int32_t nfields;         /* fields per element: 4 (acoustics: p, u, v, w) or 1
+                              (advection)                                         */
 } dgpyr_info;
 
 typedef struct dgpyr_ctx dgpyr_ctx;
@@ -339,6 +340,62 @@ void dgpyr_destroy(dgpyr_ctx* ctx);
 
 const char* dgpyr_status_string(dgpyr_status s);
 const char* dgpyr_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Linear advection u_t + div(beta u) = 0 with a constant vector beta
+ * (Section 4.1): one field per element, the same basis, cubatures, operators
+ * and matrix-core work shapes as the acoustic path (Algorithms 1-3 are stated
+ * for this equation).  With outward normal n, beta_n = beta . n and the jump
+ * [[u]] = u+ - u- (the sign for which the scheme is energy stable),
+ *   du/dt = -M^-1 (S u + L^f F),  S_ij = int_K phi_i beta . grad phi_j,
+ *   F = (beta_n - alpha |beta_n|) / 2 [[u]]  (times the face weight and sJ),
+ * alpha = 1 the upwind flux, alpha = 0 the central flux.  A face without a
+ * partner sees u+ = 0.
+ * ------------------------------------------------------------------------ */
+
+/* Mesh, read on the host during dgpyr_advection_setup only.  xyz and e2v as in
+ * dgpyr_mesh.  pair_ids (optional, [nverts]) are the vertex identities used to
+ * pair faces: two faces are neighbours when their vertex sets have equal ids,
+ * so a periodic mesh gives the vertices of opposite boundary faces equal ids
+ * (the face-point correspondence follows the ids); NULL pairs faces by the
+ * vertex indices of e2v alone. */
+typedef struct {
+  int64_t nverts;
+  const double* xyz;        /* [nverts][3]                                        */
+  int64_t nelems;
+  const int64_t* e2v;       /* [nelems][5]                                        */
+  const int64_t* pair_ids;  /* [nverts] or NULL                                   */
+} dgpyr_advection_mesh;
+
+typedef struct {
+  double beta[3];    /* advection velocity                                       */
+  double alpha;      /* 1 = upwind, 0 = central, values in [0, 1] blend          */
+  int32_t precision; /* DGPYR_FP64 (the only form built for advection)           */
+  uint32_t flags;    /* 0                                                        */
+} dgpyr_advection_opts;
+
+/* Builds an advection context: host reference data and geometry as
+ * dgpyr_setup, faces paired through pair_ids.  The state is [K][1][Np]
+ * (dgpyr_info.nfields = 1, state_len = K Np); inv_length_max is
+ * |beta| max_K |dK| / |K|.  The context then serves dgpyr_get_info, rhs, step,
+ * step_timed, pack/unpack, volume_points, project, eval, kernel_names and
+ * destroy; the acoustic-only calls (adjoint, receivers, kappa, work shapes)
+ * return E_UNSUPPORTED on it.  Synchronous.  Errors: E_ARG (null pointers,
+ * bad pair_ids, alpha outside [0, 1], flags), E_UNSUPPORTED (precision other
+ * than FP64), E_ORDER, E_MESH, E_NONCONFORMING, E_OOM, E_HIP. */
+dgpyr_status dgpyr_advection_setup(const dgpyr_advection_mesh* mesh, int32_t N,
+                                   const dgpyr_advection_opts* opts, void* stream,
+                                   dgpyr_ctx** out);
+
+/* Host-only run of what dgpyr_advection_setup does before touching the device
+ * (geometry checks and face pairing through pair_ids): nbr (optional,
+ * [nelems][5]) receives the neighbour element of each face or -1 and nface
+ * (optional, [nelems][5]) the neighbour's face (faces ordered c = -1, a = -1,
+ * a = +1, b = -1, b = +1) or -1.  Errors as the setup's host part; a periodic
+ * direction with fewer than three element layers gives faces with equal
+ * vertex-identity sets and E_NONCONFORMING. */
+dgpyr_status dgpyr_host_advection_mesh(const dgpyr_advection_mesh* mesh, int32_t N, int32_t* nbr,
+                                       int32_t* nface);
 
 #ifdef __cplusplus
 }

@@ -51,22 +51,25 @@ class AdvectionDG:
     """Advection DG right-hand side on a pyramid mesh.
 
     period: None (faces without a partner see u+ = 0) or (lo, hi): the mesh
-    fills [lo, hi]^3 and opposite boundary faces are neighbours.
+    fills [lo, hi]^3 and opposite boundary faces are neighbours.  ``elems``
+    restricts the evaluation to a subset of elements (their neighbours' traces
+    are still used); ``rhs`` then returns rows for ``self.elems`` in order.
     """
 
-    def __init__(self, xyz, e2v, N, beta, alpha=1.0, period=None, match_tol=1e-9):
+    def __init__(self, xyz, e2v, N, beta, alpha=1.0, period=None, match_tol=1e-9, elems=None):
         xyz = np.asarray(xyz, dtype=np.float64)
         e2v = np.asarray(e2v, dtype=np.int64)
         K = e2v.shape[0]
         self.N, self.Np, self.K = N, n_basis(N), K
         self.beta = np.asarray(beta, dtype=np.float64).reshape(3)
         self.alpha = float(alpha)
-        verts = xyz[e2v]
         L = None
         if period is not None:
             lo, hi = float(period[0]), float(period[1])
             L = np.full(3, hi - lo)
         self.L = L
+        S = np.arange(K) if elems is None else np.unique(np.asarray(elems, dtype=np.int64))
+        self.elems = S
 
         # ---- neighbours by face-centroid search (geometric, periodic) -------
         fcent = np.stack([xyz[e2v[:, list(fv)]].mean(axis=1) for fv in FACE_VERTS], axis=1)
@@ -76,24 +79,28 @@ class AdvectionDG:
         if L is None:
             tree = cKDTree(pts)
         else:
-            shifted = np.mod(pts - lo, L)
-            shifted[shifted >= L - tol] = 0.0
-            tree = cKDTree(shifted, boxsize=L)
-            pts = shifted
-        nb_elem = -np.ones((K, 5), dtype=np.int64)
-        nb_face = -np.ones((K, 5), dtype=np.int64)
+            pts = np.mod(pts - lo, L)
+            pts[pts >= L - tol] = 0.0
+            tree = cKDTree(pts, boxsize=L)
+        nb_elem = -np.ones((S.size, 5), dtype=np.int64)
+        nb_face = -np.ones((S.size, 5), dtype=np.int64)
         for f in range(5):
-            hits = tree.query_ball_point(pts.reshape(K, 5, 3)[:, f], r=tol)
-            for e, h in enumerate(hits):
-                others = [x for x in h if x != e * 5 + f]
+            hits = tree.query_ball_point(pts.reshape(K, 5, 3)[S, f], r=tol)
+            for row, h in enumerate(hits):
+                others = [x for x in h if x != S[row] * 5 + f]
                 if len(others) > 1:
                     raise ValueError("face matched more than one neighbour")
                 if others:
-                    nb_elem[e, f], nb_face[e, f] = divmod(others[0], 5)
+                    nb_elem[row, f], nb_face[row, f] = divmod(others[0], 5)
         self.nb_elem, self.nb_face = nb_elem, nb_face
+        active = np.unique(np.concatenate([S, nb_elem[nb_elem >= 0]]))
+        pos = -np.ones(K, dtype=np.int64)
+        pos[active] = np.arange(active.size)
+        self.active, self._pos = active, pos
 
-        # ---- volume: reference operators and geometry -----------------------
+        # ---- volume: reference operators and geometry on S ------------------
         vr = volume_rule(N)
+        verts = xyz[e2v[S]]
         self.vr, self.verts = vr, verts
         self.V, self.Dr, self.Ds, self.Dt = eval_basis_rst(N, vr["r"], vr["s"], vr["t"], deriv=True)
         G = jacobian_matrix(verts, vr["r"], vr["s"], vr["t"])
@@ -105,14 +112,16 @@ class AdvectionDG:
         self.M = np.einsum("qi,eq,qj->eij", self.V, self.wJ, self.V, optimize=True)
         self.Minv = np.linalg.inv(self.M)
 
-        # ---- faces: normals, weights, point matching -------------------------
+        # ---- faces: normals and weights on S, points matched on the active set
         xs, ns, ws, frules = _face_geometry(verts, N)
         self.fn, self.fw = ns, ws
         self.Vf = [eval_basis_rst(N, fr["r"], fr["s"], fr["t"]) for fr in frules]
+        verts_A = xyz[e2v[active]]
+        xs_A = [map_points(verts_A, fr["r"], fr["s"], fr["t"]) for fr in frules]
         self.perm = []
         for f in range(5):
             nq = self.Vf[f].shape[0]
-            perm = np.zeros((K, nq), dtype=np.int64)
+            perm = np.zeros((S.size, nq), dtype=np.int64)
             for f2 in range(5):
                 sel = np.where((nb_elem[:, f] >= 0) & (nb_face[:, f] == f2))[0]
                 if sel.size == 0:
@@ -120,7 +129,7 @@ class AdvectionDG:
                 if self.Vf[f2].shape[0] != nq:
                     raise ValueError("face type mismatch between neighbours")
                 X = xs[f][sel]
-                Y = xs[f2][nb_elem[sel, f]]
+                Y = xs_A[f2][pos[nb_elem[sel, f]]]
                 d = np.linalg.norm(_wrap_diff(X[:, :, None, :] - Y[:, None, :, :], L), axis=3)
                 am = d.argmin(axis=2)
                 dmin = np.take_along_axis(d, am[:, :, None], axis=2)[..., 0]
@@ -131,31 +140,32 @@ class AdvectionDG:
                 perm[sel] = am
             self.perm.append(perm)
 
-    def traces(self, u):
-        """u^- at the points of each face: list of (K, nq)."""
-        return [u @ Vf.T for Vf in self.Vf]
-
     def jumps(self, u):
-        """Per face: (u- (K, nq), u+ (K, nq), beta_n (K, nq))."""
-        T = self.traces(u)
+        """Per face, for the rows of S: (u- (nS, nq), u+ (nS, nq), beta_n (nS, nq)).
+        u is the full (K, Np) array."""
+        u = np.asarray(u, dtype=np.float64)
+        uA = u[self.active]
+        T = [uA @ Vf.T for Vf in self.Vf]
+        rowS = self._pos[self.elems]
         out = []
         for f in range(5):
-            um = T[f]
+            um = T[f][rowS]
             up = np.zeros_like(um)
             for f2 in range(5):
                 sel = np.where((self.nb_elem[:, f] >= 0) & (self.nb_face[:, f] == f2))[0]
                 if sel.size:
-                    src = T[f2][self.nb_elem[sel, f]]
+                    src = T[f2][self._pos[self.nb_elem[sel, f]]]
                     up[sel] = np.take_along_axis(src, self.perm[f][sel], axis=1)
             bn = self.fn[f] @ self.beta
             out.append((um, up, bn))
         return out
 
     def rhs(self, u):
-        """du/dt for u of shape (K, Np)."""
+        """du/dt on the rows of S for the full coefficient array u (K, Np)."""
         u = np.asarray(u, dtype=np.float64)
+        uS = u[self.elems]
         # volume (Algorithm 1): beta . grad u at the cubature points
-        dU = np.stack([u @ D.T for D in (self.Dr, self.Ds, self.Dt)])  # (3, K, Nc)
+        dU = np.stack([uS @ D.T for D in (self.Dr, self.Ds, self.Dt)])  # (3, nS, Nc)
         grad = np.einsum("eqmd,meq->eqd", self.Ginv, dU)
         bgrad = grad @ self.beta
         tot = (self.wJ * bgrad) @ self.V
@@ -184,11 +194,11 @@ class AdvectionDG:
         return rate
 
     def points(self):
-        """Physical volume cubature points (K, Nc, 3)."""
+        """Physical volume cubature points of the elements of S (nS, Nc, 3)."""
         return map_points(self.verts, self.vr["r"], self.vr["s"], self.vr["t"])
 
     def project(self, fun):
-        """L2 projection of fun(x (K, Nc, 3)) -> (K, Nc) onto each element's basis."""
+        """L2 projection of fun(x (nS, Nc, 3)) -> (nS, Nc) onto the basis of each element of S."""
         f = fun(self.points())
         return np.einsum("eij,ej->ei", self.Minv, (self.wJ * f) @ self.V)
 

@@ -15,7 +15,7 @@ import numpy as np
 from . import _binding as B
 from ._binding import DgpyrError
 
-__all__ = ["Solver", "Batch", "DgpyrError", "n_basis", "LSRK_CFL_CONSTANT"]
+__all__ = ["Solver", "Advection", "Batch", "DgpyrError", "n_basis", "LSRK_CFL_CONSTANT"]
 
 
 def n_basis(N: int) -> int:
@@ -119,15 +119,19 @@ class Solver:
         self._h = handle
         info = B.Info()
         B.check(L.dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
-        self.info = {k: getattr(info, k) for k, _ in B.Info._fields_}
-        self.N, self.Np, self.K = info.N, info.Np, info.nelems
-        self.state_len, self.canon_len = info.state_len, info.canon_len
+        self._set_info(info)
         if groups_per_wave:
             self.set_groups(groups_per_wave)
         if lds_operators is not None:
             self.set_operator_staging(lds_operators)
         if trace_groups:
             self.set_trace_groups(trace_groups)
+
+    def _set_info(self, info):
+        self.info = {k: getattr(info, k) for k, _ in B.Info._fields_}
+        self.N, self.Np, self.K = info.N, info.Np, info.nelems
+        self.nfields = info.nfields
+        self.state_len, self.canon_len = info.state_len, info.canon_len
 
     def set_trace_groups(self, groups: int):
         """Element groups per wave of the trace kernel (0 = default)."""
@@ -144,7 +148,7 @@ class Solver:
         return torch.empty(self.state_len, dtype=torch.float64, device="cuda")
 
     def pack(self, canon, out=None, stream=None):
-        """Canonical (K, 4, Np) device tensor -> state array."""
+        """Canonical (K, nfields, Np) device tensor -> state array."""
         out = self.empty_state() if out is None else out
         B.check(B.lib().dgpyr_pack(self._h, _dptr(canon, self.canon_len, "canon"),
                                    _dptr(out, self.state_len, "U"), _stream_handle(stream)),
@@ -154,7 +158,7 @@ class Solver:
     def unpack(self, U, out=None, stream=None):
         import torch
         if out is None:
-            out = torch.empty((self.K, 4, self.Np), dtype=torch.float64, device="cuda")
+            out = torch.empty((self.K, self.nfields, self.Np), dtype=torch.float64, device="cuda")
         B.check(B.lib().dgpyr_unpack(self._h, _dptr(U, self.state_len, "U"),
                                      _dptr(out, self.canon_len, "canon"), _stream_handle(stream)),
                 "dgpyr_unpack")
@@ -229,20 +233,21 @@ class Solver:
         return xyz, wJ
 
     def project(self, f, out=None, stream=None):
-        """L2 projection of values f (K, 4, Nc) at the cubature points -> state."""
+        """L2 projection of values f (K, nfields, Nc) at the cubature points -> state."""
         out = self.empty_state() if out is None else out
-        B.check(B.lib().dgpyr_project(self._h, _dptr(f, self.K * 4 * self.info["Nc"], "f"),
+        B.check(B.lib().dgpyr_project(self._h, _dptr(f, self.K * self.nfields * self.info["Nc"], "f"),
                                       _dptr(out, self.state_len, "U"), _stream_handle(stream)),
                 "dgpyr_project")
         return out
 
     def evaluate(self, U, out=None, stream=None):
-        """Values (K, 4, Nc) of state U at the cubature points."""
+        """Values (K, nfields, Nc) of state U at the cubature points."""
         import torch
         if out is None:
-            out = torch.empty((self.K, 4, self.info["Nc"]), dtype=torch.float64, device="cuda")
+            out = torch.empty((self.K, self.nfields, self.info["Nc"]), dtype=torch.float64,
+                              device="cuda")
         B.check(B.lib().dgpyr_eval(self._h, _dptr(U, self.state_len, "U"),
-                                   _dptr(out, self.K * 4 * self.info["Nc"], "f"),
+                                   _dptr(out, self.K * self.nfields * self.info["Nc"], "f"),
                                    _stream_handle(stream)), "dgpyr_eval")
         return out
 
@@ -286,12 +291,54 @@ class _GroupView(Solver):
         self._h = handle
         info = B.Info()
         B.check(L.dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
-        self.info = {k: getattr(info, k) for k, _ in B.Info._fields_}
-        self.N, self.Np, self.K = info.N, info.Np, info.nelems
-        self.state_len, self.canon_len = info.state_len, info.canon_len
+        self._set_info(info)
 
     def close(self):
         self._h = None
+
+
+class Advection(Solver):
+    """Linear advection u_t + div(beta u) = 0 (Section 4.1) on a pyramid mesh:
+    one field per element, state (K, 1, Np).  ``pair_ids`` ([nverts], optional)
+    pair faces through vertex identities (periodic meshes); alpha = 1 upwind,
+    0 central.  Serves rhs, step, project, evaluate, volume_points, stable_dt
+    (CFL against |beta| max |dK| / |K|)."""
+
+    def __init__(self, xyz, e2v, N, beta, alpha=1.0, pair_ids=None, precision="fp64",
+                 stream=None):  # noqa: D107
+        L = B.lib()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._e2v = np.ascontiguousarray(e2v, dtype=np.int64)
+        if self._xyz.ndim != 2 or self._xyz.shape[1] != 3:
+            raise ValueError("xyz must have shape (nverts, 3)")
+        if self._e2v.ndim != 2 or self._e2v.shape[1] != 5:
+            raise ValueError("e2v must have shape (nelems, 5)")
+        self._pid = None
+        if pair_ids is not None:
+            self._pid = np.ascontiguousarray(pair_ids, dtype=np.int64)
+            if self._pid.shape != (self._xyz.shape[0],):
+                raise ValueError("pair_ids must have shape (nverts,)")
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        mesh = B.AdvectionMesh(
+            nverts=self._xyz.shape[0],
+            xyz=self._xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            nelems=self._e2v.shape[0], e2v=self._e2v.ctypes.data_as(i64),
+            pair_ids=None if self._pid is None else self._pid.ctypes.data_as(i64))
+        b = [float(x) for x in beta]
+        if len(b) != 3:
+            raise ValueError("beta must have 3 components")
+        opts = B.AdvectionOpts(beta=(ctypes.c_double * 3)(*b), alpha=float(alpha),
+                               precision=B.PRECISION[precision], flags=0)
+        handle = ctypes.c_void_p()
+        st = L.dgpyr_advection_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
+                                     _stream_handle(stream) if stream is not None else None,
+                                     ctypes.byref(handle))
+        B.check(st, "dgpyr_advection_setup")
+        self._h = handle
+        info = B.Info()
+        B.check(L.dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
+        self._set_info(info)
+        self.beta = np.array(b)
 
 
 class Batch:

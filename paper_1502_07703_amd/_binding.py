@@ -31,6 +31,7 @@ EXPORTS = (
     "dgpyr_destroy", "dgpyr_status_string", "dgpyr_last_error",
     "dgpyr_batch_setup", "dgpyr_batch_info", "dgpyr_batch_problem", "dgpyr_batch_group",
     "dgpyr_batch_step", "dgpyr_batch_tune", "dgpyr_batch_destroy",
+    "dgpyr_advection_setup", "dgpyr_host_advection_mesh",
 )
 
 
@@ -65,8 +66,23 @@ class Info(ctypes.Structure):
         ("N", c_int32), ("Np", c_int32), ("Nc", c_int32), ("Nfc", c_int32),
         ("nelems", c_int64), ("state_len", c_int64), ("canon_len", c_int64),
         ("inv_length_max", c_double), ("hex_groups", c_int32), ("precision", c_int32),
-        ("device_bytes", c_int64), ("groups_per_wave", c_int32), ("reserved", c_int32),
+        ("device_bytes", c_int64), ("groups_per_wave", c_int32), ("nfields", c_int32),
     ]
+
+
+class AdvectionMesh(ctypes.Structure):
+    _fields_ = [
+        ("nverts", c_int64),
+        ("xyz", POINTER(c_double)),
+        ("nelems", c_int64),
+        ("e2v", POINTER(c_int64)),
+        ("pair_ids", POINTER(c_int64)),
+    ]
+
+
+class AdvectionOpts(ctypes.Structure):
+    _fields_ = [("beta", c_double * 3), ("alpha", c_double), ("precision", c_int32),
+                ("flags", c_uint32)]
 
 
 class DgpyrError(RuntimeError):
@@ -90,6 +106,12 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     L.dgpyr_setup.argtypes = [POINTER(Mesh), c_int32, POINTER(Opts), c_void_p, POINTER(c_void_p)]
     L.dgpyr_setup.restype = c_int32
+    L.dgpyr_advection_setup.argtypes = [POINTER(AdvectionMesh), c_int32, POINTER(AdvectionOpts),
+                                        c_void_p, POINTER(c_void_p)]
+    L.dgpyr_advection_setup.restype = c_int32
+    L.dgpyr_host_advection_mesh.argtypes = [POINTER(AdvectionMesh), c_int32, POINTER(c_int32),
+                                            POINTER(c_int32)]
+    L.dgpyr_host_advection_mesh.restype = c_int32
     L.dgpyr_get_info.argtypes = [c_void_p, POINTER(Info)]
     L.dgpyr_get_info.restype = c_int32
     for name in ("dgpyr_pack", "dgpyr_unpack"):

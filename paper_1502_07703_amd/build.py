@@ -29,6 +29,8 @@ SOURCES = [
     "batch.hip",
     "kernels_adjoint.hip",
     "adjoint.hip",
+    "kernels_advection.hip",
+    "advection.hip",
     "host/refops.cpp",
     "host/mesh.cpp",
 ]

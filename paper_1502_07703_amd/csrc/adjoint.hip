@@ -46,7 +46,7 @@ dgpyr_status upload_vec(dgpyr_ctx* c, const std::vector<T>& h, const T** out, co
 extern "C" {
 
 dgpyr_status dgpyr_set_kappa(dgpyr_ctx* c, const double* kappa) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (!kappa) return fail(DGPYR_E_ARG, "kappa is null");
   for (int64_t e = 0; e < c->K; ++e)
     if (!(kappa[e] > 0)) return fail(DGPYR_E_ARG, "kappa must be positive");
@@ -61,7 +61,7 @@ dgpyr_status dgpyr_set_kappa(dgpyr_ctx* c, const double* kappa) {
 }
 
 dgpyr_status dgpyr_set_receivers(dgpyr_ctx* c, int32_t nrec, const double* xyz) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (nrec < 0 || (nrec > 0 && !xyz)) return fail(DGPYR_E_ARG, "bad receiver list");
   if (nrec == 0) {
     c->nrec = 0;
@@ -86,14 +86,14 @@ dgpyr_status dgpyr_set_receivers(dgpyr_ctx* c, int32_t nrec, const double* xyz) 
 }
 
 dgpyr_status dgpyr_receivers_sample(dgpyr_ctx* c, const double* U, double* out, void* stream) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (!U || (c->nrec > 0 && !out)) return fail(DGPYR_E_ARG, "null array");
   hipError_t e = dgpyr::launch_rec_sample(*c, U, out, (hipStream_t)stream);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "receiver sample");
 }
 
 dgpyr_status dgpyr_receivers_inject(dgpyr_ctx* c, double* Ubar, const double* coef, void* stream) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (!Ubar || (c->nrec > 0 && !coef)) return fail(DGPYR_E_ARG, "null array");
   hipError_t e = dgpyr::launch_rec_inject(*c, Ubar, coef, (hipStream_t)stream);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "receiver inject");
@@ -101,7 +101,7 @@ dgpyr_status dgpyr_receivers_inject(dgpyr_ctx* c, double* Ubar, const double* co
 
 dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* c, const double* U0, double* Ubar, double* grad,
                                 double t0, double dt, void* stream) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (!U0 || !Ubar || !grad) return fail(DGPYR_E_ARG, "null array");
   if (c->alpha != 0.0)
     return fail(DGPYR_E_UNSUPPORTED, "the kappa gradient is built for the central flux (alpha = 0)");

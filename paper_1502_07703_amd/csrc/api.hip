@@ -148,6 +148,7 @@ const char* kNamesFused = "trace;stage";
 const char* kNamesSplit = "trace;volume;surface_update";
 
 const char* kernel_names(const dgpyr_ctx* c) {
+  if (c->physics == dgpyr::kAdvection) return kNamesFused;
   return (c->reference_kernels || c->unfused) ? kNamesSplit : kNamesFused;
 }
 
@@ -157,6 +158,16 @@ const char* kernel_names(const dgpyr_ctx* c) {
 // volume, surface + update.
 hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, double* R, double ra,
                      double rb, double dt, hipStream_t s, LaunchTimer* tm) {
+  if (c->physics == dgpyr::kAdvection) {
+    if (tm) tm->begin(0);
+    hipError_t e = dgpyr::launch_adv_trace(*c, U, c->T, s);
+    if (tm) tm->end();
+    if (e != hipSuccess) return e;
+    if (tm) tm->begin(1);
+    e = dgpyr::launch_adv_stage(*c, mode, U, c->T, out, R, ra, rb, dt, s);
+    if (tm) tm->end();
+    return e;
+  }
   if (c->sum_factorized) {
     if (tm) tm->begin(0);
     hipError_t e = dgpyr::launch_trace_sf(*c, U, c->T, s);
@@ -334,6 +345,13 @@ dgpyr_status check_ctx(const dgpyr_ctx* c) {
   return DGPYR_OK;
 }
 
+dgpyr_status check_acoustic(const dgpyr_ctx* c) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (c->physics != dgpyr::kAcoustic)
+    return fail(DGPYR_E_UNSUPPORTED, "this call is built for the acoustic equations only");
+  return DGPYR_OK;
+}
+
 }  // namespace api
 }  // namespace dgpyr
 
@@ -366,6 +384,90 @@ namespace api {
 // Setup shared by dgpyr_setup and the batch: dtscale (optional, [K]) is the
 // per-element time-step scale; src_range (optional) limits each source's
 // element search.
+// Per-element geometry, connectivity, materials, sources and the step clock.
+dgpyr_status upload_mesh(dgpyr_ctx* c, const dgpyr::MeshData& md) {
+  dgpyr_status st = DGPYR_OK;
+  if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
+  if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
+  if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
+  if (st == DGPYR_OK && md.nsrc > 0) {
+    c->nsrc = md.nsrc;
+    st = upload(c, md.src_of, &c->mesh.src_of, "src_of");
+    if (st == DGPYR_OK) st = upload(c, md.src_phi, &c->mesh.src_phi, "src_phi");
+    if (st == DGPYR_OK) st = upload(c, md.src_par, &c->mesh.src_par, "src_par");
+  }
+  if (st == DGPYR_OK) {
+    std::vector<double> zero(2, 0.0);
+    const double* pc = nullptr;
+    st = upload(c, zero, &pc, "clock");
+    c->clock = const_cast<double*>(pc);
+  }
+  return st;
+}
+
+// Reference operators, fragments, per-element data and work buffers of a
+// context whose sizes, physics and precision are set.
+dgpyr_status upload_context(dgpyr_ctx* c, const dgpyr::RefOps& ops, const dgpyr::MeshData& md) {
+  std::vector<int> perm((size_t)10 * ops.Nfq);
+  for (int o = 0; o < 8; ++o) dgpyr::quad_perm(c->N, o, &perm[(size_t)o * ops.Nfq]);
+  for (int o = 0; o < 2; ++o) dgpyr::tri_perm(c->N, o, &perm[(size_t)(8 + o) * ops.Nfq]);
+
+  dgpyr_status st = DGPYR_OK;
+#define UP(vec, field) \
+  if (st == DGPYR_OK) st = upload(c, vec, &c->ops.field, #field);
+  UP(transpose(ops.Dr, ops.Nc, ops.Np), DrT)
+  UP(transpose(ops.Ds, ops.Nc, ops.Np), DsT)
+  UP(transpose(ops.Dt, ops.Nc, ops.Np), DtT)
+  UP(ops.V, V)
+  UP(transpose(ops.Vf, ops.Nfc, ops.Np), VfT)
+  UP(ops.Vf, Vf)
+  UP(ops.wv, wv)
+  UP(ops.wf, wf)
+  UP(ops.fa, fa)
+  UP(ops.fb, fb)
+  UP(ops.xg, xg)
+  UP(ops.na, na)
+  UP(ops.nb, nb)
+  UP(ops.wwc, wwc)
+  UP(perm, perm)
+#undef UP
+  if (st == DGPYR_OK) st = upload(c, ops.xc, &c->xc, "xc");
+  if (st != DGPYR_OK || c->physics != dgpyr::kAcoustic) {
+    // advection: FP64 fragments only
+    if (st == DGPYR_OK) st = upload_frags<double>(c, ops);
+    if (st == DGPYR_OK) st = upload_mesh(c, md);
+    if (st == DGPYR_OK)
+      st = alloc(c, (size_t)c->K * c->Nfc * c->nfields * sizeof(double), &c->T, "trace buffer");
+    return st;
+  }
+  if (st == DGPYR_OK) st = upload(c, ops.sfLa, &c->sf.La, "sfLa");
+  if (st == DGPYR_OK) st = upload(c, ops.sfDa, &c->sf.Da, "sfDa");
+  if (st == DGPYR_OK) st = upload(c, ops.sfLe, &c->sf.Le, "sfLe");
+  if (st == DGPYR_OK) st = upload(c, ops.sfG, &c->sf.G, "sfG");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGt, &c->sf.Gt, "sfGt");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGp, &c->sf.Gp, "sfGp");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGb, &c->sf.Gb, "sfGb");
+  if (st == DGPYR_OK) st = upload(c, ops.sfGf, &c->sf.Gf, "sfGf");
+  if (st == DGPYR_OK) st = upload(c, ops.wc, &c->sf.wc, "sfwc");
+  if (st == DGPYR_OK)
+    st = c->precision == DGPYR_SPLIT_BF16 ? upload_bf16(c, ops)
+         : c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops)
+                                           : upload_frags<double>(c, ops);
+  {  // FP64 fragments of the transposed operator
+    const double* pd = nullptr;
+    if (st == DGPYR_OK && (st = upload(c, frag_rows<double>(ops.V, ops.Nc, ops.Np), &pd, "VrF")) == DGPYR_OK) c->adj.VrF = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Dr, ops.Nc, ops.Np), &pd, "DrP")) == DGPYR_OK) c->adj.DrP = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Ds, ops.Nc, ops.Np), &pd, "DsP")) == DGPYR_OK) c->adj.DsP = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Dt, ops.Nc, ops.Np), &pd, "DtP")) == DGPYR_OK) c->adj.DtP = pd;
+    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Vf, ops.Nfc, ops.Np), &pd, "LfP")) == DGPYR_OK) c->adj.LfP = pd;
+  }
+  if (st == DGPYR_OK) st = upload_mesh(c, md);
+  if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->T, "trace buffer");
+  if (st == DGPYR_OK && (c->reference_kernels || c->unfused))
+    st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->vol, "volume buffer");
+  return st;
+}
+
 dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts,
                         const double* dtscale, const int64_t* src_range, dgpyr_ctx** out) {
   if (!out) return fail(DGPYR_E_ARG, "out is null");
@@ -450,69 +552,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   // N = 5 at 196608 pyramids: 3.84 -> 4.64 ms), so it is on for FP32 only.
   c->lds_operators = opts->precision == DGPYR_FP32_MFMA;
 
-  std::vector<int> perm((size_t)10 * ops.Nfq);
-  for (int o = 0; o < 8; ++o) dgpyr::quad_perm(N, o, &perm[(size_t)o * ops.Nfq]);
-  for (int o = 0; o < 2; ++o) dgpyr::tri_perm(N, o, &perm[(size_t)(8 + o) * ops.Nfq]);
-
-  dgpyr_status st = DGPYR_OK;
-#define UP(vec, field) \
-  if (st == DGPYR_OK) st = upload(c, vec, &c->ops.field, #field);
-  UP(transpose(ops.Dr, ops.Nc, ops.Np), DrT)
-  UP(transpose(ops.Ds, ops.Nc, ops.Np), DsT)
-  UP(transpose(ops.Dt, ops.Nc, ops.Np), DtT)
-  UP(ops.V, V)
-  UP(transpose(ops.Vf, ops.Nfc, ops.Np), VfT)
-  UP(ops.Vf, Vf)
-  UP(ops.wv, wv)
-  UP(ops.wf, wf)
-  UP(ops.fa, fa)
-  UP(ops.fb, fb)
-  UP(ops.xg, xg)
-  UP(ops.na, na)
-  UP(ops.nb, nb)
-  UP(ops.wwc, wwc)
-  UP(perm, perm)
-#undef UP
-  if (st == DGPYR_OK) st = upload(c, ops.xc, &c->xc, "xc");
-  if (st == DGPYR_OK) st = upload(c, ops.sfLa, &c->sf.La, "sfLa");
-  if (st == DGPYR_OK) st = upload(c, ops.sfDa, &c->sf.Da, "sfDa");
-  if (st == DGPYR_OK) st = upload(c, ops.sfLe, &c->sf.Le, "sfLe");
-  if (st == DGPYR_OK) st = upload(c, ops.sfG, &c->sf.G, "sfG");
-  if (st == DGPYR_OK) st = upload(c, ops.sfGt, &c->sf.Gt, "sfGt");
-  if (st == DGPYR_OK) st = upload(c, ops.sfGp, &c->sf.Gp, "sfGp");
-  if (st == DGPYR_OK) st = upload(c, ops.sfGb, &c->sf.Gb, "sfGb");
-  if (st == DGPYR_OK) st = upload(c, ops.sfGf, &c->sf.Gf, "sfGf");
-  if (st == DGPYR_OK) st = upload(c, ops.wc, &c->sf.wc, "sfwc");
-  if (st == DGPYR_OK)
-    st = c->precision == DGPYR_SPLIT_BF16 ? upload_bf16(c, ops)
-         : c->precision == DGPYR_FP32_MFMA ? upload_frags<float>(c, ops)
-                                           : upload_frags<double>(c, ops);
-  {  // FP64 fragments of the transposed operator
-    const double* pd = nullptr;
-    if (st == DGPYR_OK && (st = upload(c, frag_rows<double>(ops.V, ops.Nc, ops.Np), &pd, "VrF")) == DGPYR_OK) c->adj.VrF = pd;
-    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Dr, ops.Nc, ops.Np), &pd, "DrP")) == DGPYR_OK) c->adj.DrP = pd;
-    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Ds, ops.Nc, ops.Np), &pd, "DsP")) == DGPYR_OK) c->adj.DsP = pd;
-    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Dt, ops.Nc, ops.Np), &pd, "DtP")) == DGPYR_OK) c->adj.DtP = pd;
-    if (st == DGPYR_OK && (st = upload(c, frag_proj<double>(ops.Vf, ops.Nfc, ops.Np), &pd, "LfP")) == DGPYR_OK) c->adj.LfP = pd;
-  }
-  if (st == DGPYR_OK) st = upload(c, md.verts, &c->mesh.verts, "verts");
-  if (st == DGPYR_OK) st = upload(c, md.conn, &c->mesh.conn, "conn");
-  if (st == DGPYR_OK) st = upload(c, md.mat, &c->mesh.mat, "mat");
-  if (st == DGPYR_OK && md.nsrc > 0) {
-    c->nsrc = md.nsrc;
-    st = upload(c, md.src_of, &c->mesh.src_of, "src_of");
-    if (st == DGPYR_OK) st = upload(c, md.src_phi, &c->mesh.src_phi, "src_phi");
-    if (st == DGPYR_OK) st = upload(c, md.src_par, &c->mesh.src_par, "src_par");
-  }
-  if (st == DGPYR_OK) {
-    std::vector<double> zero(2, 0.0);
-    const double* pc = nullptr;
-    st = upload(c, zero, &pc, "clock");
-    c->clock = const_cast<double*>(pc);
-  }
-  if (st == DGPYR_OK) st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->T, "trace buffer");
-  if (st == DGPYR_OK && (c->reference_kernels || c->unfused))
-    st = alloc(c, (size_t)c->K * 4 * c->Np * sizeof(double), &c->vol, "volume buffer");
+  dgpyr_status st = upload_context(c, ops, md);
   if (st != DGPYR_OK) {
     free_ctx(c);
     return st;
@@ -543,21 +583,21 @@ dgpyr_status dgpyr_get_info(const dgpyr_ctx* c, dgpyr_info* info) {
   info->Nc = c->Nc;
   info->Nfc = c->Nfc;
   info->nelems = c->K;
-  info->state_len = c->K * 4 * c->Np;
-  info->canon_len = c->K * 4 * c->Np;
+  info->state_len = c->K * c->nfields * c->Np;
+  info->canon_len = c->K * c->nfields * c->Np;
   info->inv_length_max = c->inv_length_max;
   info->hex_groups = c->hex_groups ? 1 : 0;
   info->precision = c->precision;
   info->device_bytes = c->device_bytes;
   info->groups_per_wave = c->mfma_groups;
-  info->reserved = 0;
+  info->nfields = c->nfields;
   return DGPYR_OK;
 }
 
 dgpyr_status dgpyr_pack(dgpyr_ctx* c, const double* canon, double* U, void* stream) {
   if (dgpyr_status s = check_ctx(c)) return s;
   if (!canon || !U) return fail(DGPYR_E_ARG, "null array");
-  hipError_t e = hipMemcpyAsync(U, canon, (size_t)c->K * 4 * c->Np * sizeof(double),
+  hipError_t e = hipMemcpyAsync(U, canon, (size_t)c->K * c->nfields * c->Np * sizeof(double),
                                 hipMemcpyDeviceToDevice, (hipStream_t)stream);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "pack");
 }
@@ -565,7 +605,7 @@ dgpyr_status dgpyr_pack(dgpyr_ctx* c, const double* canon, double* U, void* stre
 dgpyr_status dgpyr_unpack(dgpyr_ctx* c, const double* U, double* canon, void* stream) {
   if (dgpyr_status s = check_ctx(c)) return s;
   if (!canon || !U) return fail(DGPYR_E_ARG, "null array");
-  hipError_t e = hipMemcpyAsync(canon, U, (size_t)c->K * 4 * c->Np * sizeof(double),
+  hipError_t e = hipMemcpyAsync(canon, U, (size_t)c->K * c->nfields * c->Np * sizeof(double),
                                 hipMemcpyDeviceToDevice, (hipStream_t)stream);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "unpack");
 }
@@ -642,7 +682,7 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, dou
 }
 
 dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* c, const double* lam, double* out, void* stream) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (!lam || !out) return fail(DGPYR_E_ARG, "null array");
   if ((const double*)out == lam) return fail(DGPYR_E_ARG, "lam and out must not alias");
   hipStream_t s = (hipStream_t)stream;
@@ -658,7 +698,7 @@ dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* c, const double* lam, double* out, voi
 }
 
 dgpyr_status dgpyr_set_trace_groups(dgpyr_ctx* c, int32_t groups) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (groups != 0 && groups != 1 && groups != 2 && groups != 4)
     return fail(DGPYR_E_ARG, "trace groups must be 0, 1, 2 or 4");
   c->trace_groups = groups;
@@ -666,13 +706,13 @@ dgpyr_status dgpyr_set_trace_groups(dgpyr_ctx* c, int32_t groups) {
 }
 
 dgpyr_status dgpyr_set_operator_staging(dgpyr_ctx* c, int32_t enable) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   c->lds_operators = enable != 0;
   return DGPYR_OK;
 }
 
 dgpyr_status dgpyr_set_groups(dgpyr_ctx* c, int32_t groups) {
-  if (dgpyr_status s = check_ctx(c)) return s;
+  if (dgpyr_status s = check_acoustic(c)) return s;
   if (groups < 0 || groups > 2) return fail(DGPYR_E_ARG, "groups_per_wave must be 0, 1 or 2");
   c->mfma_groups = groups == 0 ? default_groups(c->N, c->precision) : groups;
   return DGPYR_OK;

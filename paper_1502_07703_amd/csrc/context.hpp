@@ -111,8 +111,23 @@ struct DevMesh {
 
 }  // namespace dgpyr
 
+namespace dgpyr {
+// Equation a context discretises.
+constexpr int kAcoustic = 0;   // first-order acoustics, 4 fields (Section 4.3)
+constexpr int kAdvection = 1;  // linear advection, 1 field (Section 4.1)
+
+// Advection velocity and flux parameter, by value in kernel arguments.
+struct AdvParams {
+  double beta[3];
+  double alpha;
+};
+}  // namespace dgpyr
+
 struct dgpyr_ctx {
   int N = 0, Np = 0, Nc = 0, Nfq = 0, Nfc = 0;
+  int physics = dgpyr::kAcoustic;
+  int nfields = 4;                 // fields per element: 4 (acoustics) or 1
+  dgpyr::AdvParams adv{};          // advection only
   int64_t K = 0;
   int precision = 0;
   int bc = 0;
@@ -189,6 +204,11 @@ hipError_t launch_stage_sf(const dgpyr_ctx& c, int mode, const double* U, const 
 hipError_t launch_stage_bf16(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                              double* out, double* R, double ra, double rb, double dt,
                              hipStream_t s);
+// Advection (kernels_advection.hip): traces [K][Nfc] and the fused stage.
+hipError_t launch_adv_trace(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
+hipError_t launch_adv_stage(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+                            double* out, double* R, double ra, double rb, double dt,
+                            hipStream_t s);
 // Fused volume + surface + inverse mass (+ RK stage) in one launch.
 hipError_t launch_stage_mfma(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                              double* out, double* R, double ra, double rb, double dt,

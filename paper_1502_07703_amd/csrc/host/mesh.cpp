@@ -169,8 +169,9 @@ int locate_receivers(const RefOps& ops, int nrec, const double* xyz, const doubl
 }
 
 int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nelems,
-               const int64_t* e2v, const double* rho, const double* kappa, MeshData& md,
-               std::string& err) {
+               const int64_t* e2v_geom, const double* rho, const double* kappa, MeshData& md,
+               std::string& err, const int64_t* pair_ids) {
+  const int64_t* e2v = e2v_geom;
   char buf[256];
   const int64_t K = nelems;
   md.K = K;
@@ -246,7 +247,19 @@ int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nel
     md.inv_length_max = std::max(md.inv_length_max, md.inv_length[(size_t)e]);
   }
 
-  // Faces: sort by vertex set, pair equal keys.
+  // Faces: sort by vertex set (vertex identities when given), pair equal keys.
+  std::vector<int64_t> paired;
+  if (pair_ids) {
+    for (int64_t v = 0; v < nverts; ++v)
+      if (pair_ids[v] < 0 || pair_ids[v] >= nverts) {
+        std::snprintf(buf, sizeof buf, "pair id of vertex %lld out of range", (long long)v);
+        err = buf;
+        return DGPYR_E_ARG;
+      }
+    paired.resize((size_t)K * 5);
+    for (size_t i = 0; i < paired.size(); ++i) paired[i] = pair_ids[e2v_geom[i]];
+    e2v = paired.data();
+  }
   std::vector<FaceKey> keys((size_t)K * 5);
   for (int64_t e = 0; e < K; ++e) {
     const int64_t* ev = &e2v[5 * e];

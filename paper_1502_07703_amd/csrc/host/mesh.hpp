@@ -48,8 +48,11 @@ int locate_receivers(const RefOps& ops, int nrec, const double* xyz, const doubl
                      std::string& err);
 
 // Returns 0 on success or a negative dgpyr_status with a message in err.
+// pair_ids (optional, [nverts]) replace the vertex indices when faces are
+// paired (periodic meshes give the images of a vertex one id); geometry always
+// uses xyz.
 int build_mesh(const RefOps& ops, int64_t nverts, const double* xyz, int64_t nelems,
                const int64_t* e2v, const double* rho, const double* kappa, MeshData& md,
-               std::string& err);
+               std::string& err, const int64_t* pair_ids = nullptr);
 
 }  // namespace dgpyr

@@ -32,15 +32,15 @@ __global__ void k_points(DevOps ops, DevMesh mesh, int n1, int Nc, const double*
 }
 
 // U_i = sum_q w_q J_q phi_i(q) f_q / M_ii (M diagonal, Lemma 3), per field.
-__global__ void k_project(DevOps ops, DevMesh mesh, int Np, int Nc, int n1,
+__global__ void k_project(DevOps ops, DevMesh mesh, int Np, int Nc, int n1, int nf,
                           const double* __restrict__ f, double* __restrict__ U) {
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= mesh.K * 4 * Np) return;
-  const int64_t e = gid / (4 * Np);
-  const int rem = (int)(gid - e * 4 * Np);
+  if (gid >= mesh.K * nf * Np) return;
+  const int64_t e = gid / (nf * Np);
+  const int rem = (int)(gid - e * nf * Np);
   const int fld = rem / Np, i = rem - fld * Np;
   const double* x = mesh.verts + e * 16;
-  const double* fe = f + (e * 4 + fld) * Nc;
+  const double* fe = f + (e * nf + fld) * Nc;
   double acc = 0.0;
   for (int q = 0; q < Nc; ++q) {
     const int p = q % n1, m = (q / n1) % n1;
@@ -50,10 +50,10 @@ __global__ void k_project(DevOps ops, DevMesh mesh, int Np, int Nc, int n1,
 }
 
 // f_q = sum_n phi_n(q) U_n per field.
-__global__ void k_eval(DevOps ops, int64_t K, int Np, int Nc, const double* __restrict__ U,
+__global__ void k_eval(DevOps ops, int64_t K, int Np, int Nc, int nf, const double* __restrict__ U,
                        double* __restrict__ f) {
   const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (gid >= K * 4 * Nc) return;
+  if (gid >= K * nf * Nc) return;
   const int64_t ef = gid / Nc;
   const int q = (int)(gid - ef * Nc);
   const double* u = U + ef * Np;
@@ -83,14 +83,14 @@ hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_
 }
 
 hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s) {
-  hipLaunchKernelGGL(k_project, dim3(nblocks(c.K * 4 * c.Np)), dim3(kThreads), 0, s, c.ops, c.mesh,
-                     c.Np, c.Nc, c.N + 1, f, U);
+  hipLaunchKernelGGL(k_project, dim3(nblocks(c.K * c.nfields * c.Np)), dim3(kThreads), 0, s, c.ops,
+                     c.mesh, c.Np, c.Nc, c.N + 1, c.nfields, f, U);
   return hipGetLastError();
 }
 
 hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s) {
-  hipLaunchKernelGGL(k_eval, dim3(nblocks(c.K * 4 * c.Nc)), dim3(kThreads), 0, s, c.ops, c.K, c.Np,
-                     c.Nc, U, f);
+  hipLaunchKernelGGL(k_eval, dim3(nblocks(c.K * c.nfields * c.Nc)), dim3(kThreads), 0, s, c.ops, c.K,
+                     c.Np, c.Nc, c.nfields, U, f);
   return hipGetLastError();
 }
 

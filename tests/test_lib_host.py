@@ -278,3 +278,78 @@ def test_source_location_matches_oracle(B):
             a = 2 * (1 + r[0]) / (1 - t) - 1
             b = 2 * (1 + r[1]) / (1 - t) - 1
             assert np.allclose(abc[j], [a, b, t], atol=1e-10), (k1d, j, abc[j], (a, b, t))
+
+
+def _adv_mesh(B, xyz, e2v, pid=None):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    e2v = np.ascontiguousarray(e2v, dtype=np.int64)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    keep = [xyz, e2v]
+    if pid is not None:
+        pid = np.ascontiguousarray(pid, dtype=np.int64)
+        keep.append(pid)
+    m = B.AdvectionMesh(nverts=xyz.shape[0], xyz=xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        nelems=e2v.shape[0], e2v=e2v.ctypes.data_as(i64),
+                        pair_ids=None if pid is None else pid.ctypes.data_as(i64))
+    return m, keep
+
+
+@pytest.mark.parametrize("k1d,shuffle", [(3, False), (4, True)])
+def test_host_periodic_pairing_matches_oracle(B, k1d, shuffle):
+    """Faces paired through periodic vertex identities agree with the oracle's
+    geometric matching modulo the period (neighbour element and face)."""
+    from oracle.advection import AdvectionDG
+    from synth import periodic_pair_ids
+    xyz, e2v = hex_pyramid_mesh(k1d, seed=8, lo=-1.0, hi=1.0, shuffle=shuffle)
+    m, keep = _adv_mesh(B, xyz, e2v, periodic_pair_ids(xyz))
+    K = e2v.shape[0]
+    nbr = np.empty((K, 5), dtype=np.int32)
+    nfc = np.empty((K, 5), dtype=np.int32)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    B.check(B.lib().dgpyr_host_advection_mesh(ctypes.byref(m), 1, nbr.ctypes.data_as(i32),
+                                              nfc.ctypes.data_as(i32)), "host advection mesh")
+    o = AdvectionDG(xyz, e2v, 1, [1.0, 0.0, 0.0], period=(-1.0, 1.0))
+    assert (nbr >= 0).all()
+    assert np.array_equal(nbr, o.nb_elem.astype(np.int32))
+    assert np.array_equal(nfc, o.nb_face.astype(np.int32))
+    # without identities the cube's boundary faces have no partner
+    m2, keep2 = _adv_mesh(B, xyz, e2v)
+    B.check(B.lib().dgpyr_host_advection_mesh(ctypes.byref(m2), 1, nbr.ctypes.data_as(i32), None),
+            "host advection mesh")
+    assert (nbr < 0).sum() == 6 * k1d * k1d
+
+
+def test_advection_setup_errors_before_device(B):
+    import paper_1502_07703_amd as dg
+    from synth import periodic_pair_ids
+    xyz, e2v = hex_pyramid_mesh(3, seed=1, lo=-1.0, hi=1.0)
+    pid = periodic_pair_ids(xyz)
+    beta = [1.0, 0.0, 0.0]
+    cases = [
+        (dict(N=9), B.E_ORDER),
+        (dict(alpha=1.5), B.E_ARG),
+        (dict(beta=[0.0, 0.0, 0.0]), B.E_ARG),
+        (dict(beta=[np.nan, 0.0, 0.0]), B.E_ARG),
+        (dict(precision="fp32_mfma"), B.E_UNSUPPORTED),
+    ]
+    for kw, status in cases:
+        args = dict(N=2, beta=beta, alpha=1.0, pair_ids=pid)
+        args.update(kw)
+        N = args.pop("N")
+        with pytest.raises(dg.DgpyrError) as ex:
+            dg.Advection(xyz, e2v, N, **args)
+        assert ex.value.status == status, kw
+    bad = pid.copy()
+    bad[0] = xyz.shape[0] + 3
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Advection(xyz, e2v, 2, beta, pair_ids=bad)
+    assert ex.value.status == B.E_ARG
+    # two element layers across a periodic direction: boundary faces of both
+    # layers carry the same identity sets
+    xyz2, e2v2 = hex_pyramid_mesh(2, seed=1, lo=-1.0, hi=1.0)
+    with pytest.raises(dg.DgpyrError) as ex:
+        dg.Advection(xyz2, e2v2, 2, beta, pair_ids=periodic_pair_ids(xyz2))
+    assert ex.value.status == B.E_NONCONFORMING
+    L = B.lib()
+    assert L.dgpyr_advection_setup(None, 2, None, None, None) != 0
+    assert L.dgpyr_host_advection_mesh(None, 2, None, None) != 0
