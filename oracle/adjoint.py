@@ -10,10 +10,12 @@ this module.  Plain and slow, for small meshes:
   p(x_r) = sum_i phi_i(xi_r) U_{p,i} of the element containing x_r;
 * ``misfit_gradient`` differentiates J with respect to the per-element bulk
   modulus kappa = rho c^2 by reverse-mode through every LSRK stage
-  (Algorithm 3): for the central flux (alpha = 0) the operator depends on
-  kappa_K only through the factor kappa_K of element K's pressure rows, and
-  so does the point-source term (dp/dt = -kappa M^-1 (vol + surf - b)), so
-  d(A U + b)/d kappa_K = (A U + b)_{p,K} / kappa_K.
+  (Algorithm 3).  The operator depends on kappa_K through the factor kappa_K
+  of element K's pressure rows, which the point-source term shares
+  (dp/dt = -kappa M^-1 (vol + surf - b)), giving (A U + b)_{p,K} / kappa_K,
+  and, for alpha > 0, through the penalty coefficients tau_p = alpha/{rho c},
+  tau_u = alpha {rho c} of every face of K, {rho c} = (z- + z+)/2 with
+  z = sqrt(kappa rho): ``penalty_kappa_terms`` adds those.
 
 Pinned by central finite differences of ``misfit`` in ``tests/test_oracle_adjoint.py``.
 """
@@ -68,9 +70,67 @@ def _source_fn(xyz, e2v, N, rho, kappa, bc, sources):
     return lambda t: dg.rhs(zero, t).ravel()
 
 
-def misfit(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=None, bc="wall", sources=None):
-    """J for the central-flux solver; data: (nsteps, nrec)."""
-    A = operator_matrix(xyz, e2v, N, rho=rho, kappa=kappa, bc=bc, alpha=0.0)
+def penalty_kappa_terms(dg, W, Rb):
+    """sum over faces of <Rb, d(A W)/d kappa_K> through tau (alpha > 0), for
+    every element K of ``dg`` (an AcousticDG on the whole mesh).
+
+    With P_p = (n.[[u]] - tau_p [[p]])/2 and P_u = n ([[p]] - tau_u n.[[u]])/2
+    lifted into element e's rows of A W = -Kmat M^-1 (vol + surf),
+    d/d{rho c} <Rb_e, (A W)_e> = sum_q s_e(q) with
+    s_e = -w sJ alpha/2 (mu_p [[p]] / {rho c}^2 - (n.mu_u) (n.[[u]])),
+    mu = traces of M^-1 Kmat Rb.  d{rho c}/d kappa_x = z_x / (4 kappa_x) for
+    x either side of an interior face, z_e / (2 kappa_e) on a boundary face
+    (the ghost has the element's own material)."""
+    K, Np = dg.K, dg.Np
+    W = np.asarray(W, dtype=np.float64).reshape(K, 4, Np)
+    Rb = np.asarray(Rb, dtype=np.float64).reshape(K, 4, Np)
+    rho, kap, z = dg._material(np.arange(K))
+    kfac = np.concatenate([kap[:, None], np.repeat((1.0 / rho)[:, None], 3, axis=1)], axis=1)
+    mu = np.einsum("eij,efj->efi", dg.Minv, kfac[:, :, None] * Rb)
+    TW = dg.traces(W)
+    TM = dg.traces(mu)
+    g = np.zeros(K)
+    for f in range(5):
+        Tm = TW[f]
+        n = dg.fn[f]
+        Tp = np.empty_like(Tm)
+        zP = z.copy()
+        inner = dg.nb_row[f] >= 0
+        rows = np.where(inner)[0]
+        for f2 in range(5):
+            sel = rows[dg.nb_f[f][rows] == f2]
+            if sel.size:
+                src = TW[f2][dg.nb_row[f][sel]]
+                Tp[sel] = np.take_along_axis(src, dg.nb_perm[f][sel][:, None, :], axis=2)
+        zP[rows] = z[dg.nb_row[f][rows]]
+        bnd = ~inner
+        if np.any(bnd):
+            pm, um, nb = Tm[bnd, 0], Tm[bnd, 1:4], n[bnd]
+            un = np.einsum("mdq,mqd->mq", um, nb)
+            if dg.bc == "wall":
+                Tp[bnd, 0] = pm
+                Tp[bnd, 1:4] = um - 2.0 * un[:, None, :] * np.transpose(nb, (0, 2, 1))
+            else:
+                Tp[bnd, 0] = -pm
+                Tp[bnd, 1:4] = um
+        zavg = 0.5 * (z + zP)
+        jp = Tp[:, 0] - Tm[:, 0]
+        jun = np.einsum("edq,eqd->eq", Tp[:, 1:4] - Tm[:, 1:4], n)
+        mun = np.einsum("edq,eqd->eq", TM[f][:, 1:4], n)
+        s_e = -dg.fw[f] * 0.5 * dg.alpha * (TM[f][:, 0] * jp / zavg[:, None] ** 2 - mun * jun)
+        tot = s_e.sum(axis=1)
+        # own side
+        g += np.where(inner, z / (4.0 * kap), z / (2.0 * kap)) * tot
+        # the neighbour's {rho c} on this face
+        nbr = dg.nb_row[f][rows]
+        np.add.at(g, nbr, z[nbr] / (4.0 * kap[nbr]) * tot[rows])
+    return g
+
+
+def misfit(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=None, bc="wall", sources=None,
+           alpha=0.0):
+    """J; data: (nsteps, nrec)."""
+    A = operator_matrix(xyz, e2v, N, rho=rho, kappa=kappa, bc=bc, alpha=alpha)
     b = _source_fn(xyz, e2v, N, rho, kappa, bc, sources)
     U = np.asarray(U0, dtype=np.float64).ravel().copy()
     R = np.zeros_like(U)
@@ -86,12 +146,13 @@ def misfit(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=None, bc="wall", so
 
 
 def misfit_gradient(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=None, bc="wall",
-                    sources=None):
+                    sources=None, alpha=0.0):
     """(J, dJ/dkappa [K], dJ/dU0) by the discrete adjoint of every stage."""
     K = np.asarray(e2v).shape[0]
     Np = (N + 1) * (N + 2) * (2 * N + 3) // 6
     kappa = np.asarray(kappa, dtype=np.float64)
-    A = operator_matrix(xyz, e2v, N, rho=rho, kappa=kappa, bc=bc, alpha=0.0)
+    A = operator_matrix(xyz, e2v, N, rho=rho, kappa=kappa, bc=bc, alpha=alpha)
+    dgp = AcousticDG(xyz, e2v, N, rho=rho, kappa=kappa, bc=bc, alpha=alpha) if alpha else None
     b = _source_fn(xyz, e2v, N, rho, kappa, bc, sources)
     U = np.asarray(U0, dtype=np.float64).ravel().copy()
     R = np.zeros_like(U)
@@ -124,5 +185,7 @@ def misfit_gradient(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=None, bc="
             ts = n * dt + LSRK_C[s] * dt
             AW = (A @ stages[n][s] + b(ts)) * prow
             grad += dt * (Rb * AW).reshape(K, 4 * Np).sum(axis=1) / kappa
+            if dgp is not None:
+                grad += dt * penalty_kappa_terms(dgp, stages[n][s], Rb)
             Rb = LSRK_A[s] * Rb
     return J, grad, Ub.reshape(K, 4, Np)

@@ -70,3 +70,27 @@ def test_operator_is_skew_in_energy_product_for_central_flux():
         return 0.5 * (E(x + y) - E(x) - E(y))
     lhs = inner(A @ U, V) + inner(U, A @ V)
     assert abs(lhs) <= 1e-11 * (abs(inner(A @ U, V)) + 1e-30)
+
+
+def test_kappa_gradient_with_penalty_flux_matches_central_differences():
+    """alpha = 1: kappa also enters through tau_p = alpha/{rho c} and
+    tau_u = alpha {rho c} on every face (walls and free surface)."""
+    for bc in ("wall", "free"):
+        xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, src = _setup(seed=3)
+        rho = np.random.default_rng(11).uniform(0.7, 1.4, kappa.size)
+        J, g, _ = misfit_gradient(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=rho, bc=bc,
+                                  sources=src, alpha=1.0)
+        g0 = misfit_gradient(xyz, e2v, N, kappa, U0, dt, nsteps, Rm, data, rho=rho, bc=bc,
+                             sources=src, alpha=0.0)[1]
+        rng = np.random.default_rng(7)
+        for _ in range(3):
+            d = rng.normal(size=kappa.size)
+            h = 1e-5
+            Jp = misfit(xyz, e2v, N, kappa + h * d, U0, dt, nsteps, Rm, data, rho=rho, bc=bc,
+                        sources=src, alpha=1.0)
+            Jm = misfit(xyz, e2v, N, kappa - h * d, U0, dt, nsteps, Rm, data, rho=rho, bc=bc,
+                        sources=src, alpha=1.0)
+            fd = (Jp - Jm) / (2 * h)
+            assert abs(fd - g @ d) <= 1e-7 * max(abs(fd), 1e-12), (bc, fd, g @ d)
+        # the penalty terms are not negligible here
+        assert np.abs(g - g0).max() > 1e-3 * np.abs(g).max()
