@@ -198,9 +198,11 @@ dgpyr_status dgpyr_receivers_inject(dgpyr_ctx* ctx, double* Ubar, const double* 
  * initial state is U0: on entry Ubar is the adjoint of the step's final
  * state, on exit that of U0; grad [nelems] accumulates the step's part of
  * dJ/dkappa.  The five stage inputs are recomputed from U0 (sources
- * included).  Central flux only: E_UNSUPPORTED for alpha != 0.  The first
- * call allocates nine state-sized scratch arrays held by the context.
- * Device arrays; asynchronous. */
+ * included).  kappa enters through the pressure rows' factor and, for
+ * alpha > 0, through the penalty coefficients tau_p = alpha/{rho c},
+ * tau_u = alpha {rho c} of every face (Section 4.3).  The first call
+ * allocates nine state-sized scratch arrays and one trace-sized array held by
+ * the context.  Device arrays; asynchronous. */
 dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* ctx, const double* U0, double* Ubar, double* grad,
                                 double t0, double dt, void* stream);
 

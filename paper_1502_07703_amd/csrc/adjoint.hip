@@ -6,9 +6,11 @@
 // the step's final state:
 //   Rb += b_s Ub;  grad += dt <Rb, dF/dkappa>;  Ub += dt A^T Rb;  Rb *= a_s,
 // with the stage inputs U_{s-1} recomputed from the step's initial state.
-// For the central flux (alpha = 0) kappa_K enters F only as the factor of
-// element K's pressure rows (sources included, Section 4.3), so
-// dF/dkappa_K = F_{p,K} / kappa_K.
+// kappa_K enters F as the factor of element K's pressure rows (sources
+// included, Section 4.3), giving F_{p,K} / kappa_K, and for alpha > 0 through
+// the penalty coefficients of K's faces, {rho c} = (z- + z+)/2 with
+// z = sqrt(kappa rho) (k_tau_grad, from the traces of the stage input and of
+// M^-1 Kmat Rb).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -103,8 +105,6 @@ dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* c, const double* U0, double* Ubar, do
                                 double t0, double dt, void* stream) {
   if (dgpyr_status s = check_acoustic(c)) return s;
   if (!U0 || !Ubar || !grad) return fail(DGPYR_E_ARG, "null array");
-  if (c->alpha != 0.0)
-    return fail(DGPYR_E_UNSUPPORTED, "the kappa gradient is built for the central flux (alpha = 0)");
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = c->K * 4 * c->Np;
   const size_t bytes = (size_t)n * sizeof(double);
@@ -112,6 +112,10 @@ dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* c, const double* U0, double* Ubar, do
     if (dgpyr_status st = alloc(c, 9 * bytes, &c->adj_work, "adjoint step scratch")) return st;
   if (!c->adj_mu)
     if (dgpyr_status st = alloc(c, bytes, &c->adj_mu, "adjoint scratch")) return st;
+  if (!c->adj_T)
+    if (dgpyr_status st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->adj_T,
+                                "adjoint trace scratch"))
+      return st;
   double* W = c->adj_work;  // W + s n: input of stage s
   double* Rw = W + 5 * n;
   double* Rb = W + 6 * n;
@@ -142,9 +146,12 @@ dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* c, const double* U0, double* Ubar, do
     if (e == hipSuccess) e = run_stage(c, 0, W + st * n, F, nullptr, 0.0, 0.0, 0.0, s, nullptr);
     if (e == hipSuccess) e = dgpyr::launch_kappa_grad(*c, grad, Rb, F, dt, s);
     // A^T Rb
+    // (c->T now holds the traces of the stage input W_s)
     if (e == hipSuccess) e = dgpyr::launch_adjoint_scale(*c, Rb, c->adj_mu, s);
-    if (e == hipSuccess) e = dgpyr::launch_trace_mfma(*c, c->adj_mu, c->T, s);
-    if (e == hipSuccess) e = dgpyr::launch_adjoint(*c, c->adj_mu, c->T, AT, s);
+    if (e == hipSuccess) e = dgpyr::launch_trace_mfma(*c, c->adj_mu, c->adj_T, s);
+    if (e == hipSuccess && c->alpha != 0.0)
+      e = dgpyr::launch_tau_grad(*c, grad, c->T, c->adj_T, dt, s);
+    if (e == hipSuccess) e = dgpyr::launch_adjoint(*c, c->adj_mu, c->adj_T, AT, s);
     if (e == hipSuccess) e = dgpyr::launch_adj_post(*c, Ubar, Rb, AT, dt, kRkA[st], s);
   }
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "adjoint step");

@@ -142,6 +142,7 @@ struct dgpyr_ctx {
   // reverse-step scratch (allocated on first dgpyr_adjoint_step): stage inputs
   // W[5], forward R, adjoint R, A^T output, stage right-hand side
   double* adj_work = nullptr;
+  double* adj_T = nullptr;   // [K][Nfc][4] traces of the adjoint scratch (adjoint step)
   // receivers (dgpyr_set_receivers): element and basis values phi_r [nrec][Np]
   int nrec = 0;
   const int64_t* rec_elem = nullptr;
@@ -191,6 +192,10 @@ hipError_t launch_adj_post(const dgpyr_ctx& c, double* Ub, double* Rb, const dou
                            double dt, double as, hipStream_t s);
 hipError_t launch_kappa_grad(const dgpyr_ctx& c, double* grad, const double* Rb, const double* F,
                              double dt, hipStream_t s);
+// kappa derivative through the penalty coefficients: traces of the forward
+// state TW and of M^-1 Kmat Rb TM ([K][Nfc][4] each).
+hipError_t launch_tau_grad(const dgpyr_ctx& c, double* grad, const double* TW, const double* TM,
+                           double dt, hipStream_t s);
 hipError_t launch_project(const dgpyr_ctx& c, const double* f, double* U, hipStream_t s);
 hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream_t s);
 // Matrix-core kernels (kernels_mfma.hip).

@@ -84,12 +84,13 @@ def _misfit_case(N, k1d, nsteps, nrec, seed):
     return xyz, e2v, kap, U0, pts, data, src
 
 
-def _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every, grad=True):
+def _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every, grad=True, alpha=0.0,
+                bc="wall", rho=None):
     import torch
 
     import paper_1502_07703_amd as dg
     from paper_1502_07703_amd.adjoint import receiver_misfit
-    s = dg.Solver(xyz, e2v, N, alpha=0.0, sources=src)
+    s = dg.Solver(xyz, e2v, N, alpha=alpha, bc=bc, rho=rho, sources=src)
     s.set_receivers(pts)
     U = s.pack(torch.from_numpy(U0).cuda())
     k = torch.tensor(kap, dtype=torch.float64, requires_grad=grad)
@@ -133,3 +134,23 @@ def test_misfit_gradient_central_differences():
         fd = (Jp - Jm) / (2 * h)
         log(f"[adjoint] direction {i}: fd {fd:.12e} adjoint {g @ d:.12e}")
         assert abs(fd - g @ d) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("k1d,N,bc", [(1, 2, "wall"), (1, 2, "free"), (2, 1, "wall")])
+def test_misfit_gradient_penalty_flux_matches_oracle(k1d, N, bc):
+    """alpha = 1: kappa also enters the penalty coefficients of every face;
+    heterogeneous rho, walls or free surface, interior quad faces (k1d = 2)."""
+    from oracle.adjoint import misfit_gradient, receiver_matrix
+    nsteps, dt = 6, 0.02
+    xyz, e2v, kap, U0, pts, data, src = _misfit_case(N, k1d, nsteps, 4, 3)
+    rho = np.random.default_rng(11).uniform(0.7, 1.4, kap.size)
+    Rm = receiver_matrix(xyz, e2v, N, pts)
+    J_ref, g_ref, _ = misfit_gradient(xyz, e2v, N, kap, U0, dt, nsteps, Rm, data, rho=rho, bc=bc,
+                                      sources=src, alpha=1.0)
+    log(f"[adjoint] penalty flux k1d={k1d} N={N} {bc}")
+    J, g = _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every=4, alpha=1.0,
+                       bc=bc, rho=rho)
+    assert abs(J - J_ref) <= 1e-12 * J_ref
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    log(f"[adjoint] penalty flux kappa gradient rel err {err:.2e}")
+    assert err < 1e-10
