@@ -25,3 +25,22 @@ def test_traffic_record_requires_matching_sources():
     assert bench.recorded_traffic("stage", "no such workload") is None
     v = bench.recorded_traffic("stage", "k1d=40 N=4 fp64 fused")
     assert v is None or v > 0
+
+
+def test_advection_work_is_one_field_of_the_acoustic_contractions():
+    for N in range(0, 9):
+        Np, n1 = bench.n_basis(N), N + 1
+        Nc, Nfc = n1 ** 3, 5 * n1 ** 2
+        # trace: the same V^f contraction on one field instead of four
+        assert 4 * bench.adv_work("trace", N)[0] == bench.kernel_work("trace", N)[0]
+        # stage contractions: three derivatives, projection and lift of one field
+        F, B = bench.adv_work("stage", N)
+        assert F - (10 * Nc + 8 * Nfc + 6 * Np) == 2 * (3 * Nc * Np + Nc * Np + Nfc * Np)
+        assert B == 32 * Np + 8 * n1 ** 2 + 152
+
+
+def test_plane_wave_dot_matches_matmul():
+    import numpy as np
+    P = np.random.default_rng(0).standard_normal((7, 5, 3))
+    k = np.array([1.5, -0.2, 0.7])
+    assert np.allclose(bench._dot3(P, k), P @ k, rtol=1e-15, atol=1e-15)
