@@ -8,25 +8,22 @@
 
 namespace dgpyr {
 
-// Weighted flux at face point q (face f = q / Nfq) of element e, whose
-// vertices are x (15 doubles).  Reads the element's own trace and the
-// neighbour's trace from T ([K][Nfc][4]) through the connectivity code, or
-// builds the mirror state on a boundary face.  With [[a]] = a+ - a-, outward
-// unit normal n, tau_p = alpha / {rho c}, tau_u = alpha {rho c}:
+// Weighted flux at face point q (face f = q / Nfq) of element e, given the
+// point's unit outward normal n = (n0, n1, n2) and surface Jacobian sJ.
+// Reads the element's own trace and the neighbour's trace from T
+// ([K][Nfc][4]) through the connectivity code, or builds the mirror state on
+// a boundary face.  With [[a]] = a+ - a-, tau_p = alpha / {rho c},
+// tau_u = alpha {rho c}:
 //   F[0]   = w sJ (n.[[u]] - tau_p [[p]]) / 2
 //   F[1+k] = w sJ n_k ([[p]] - tau_u n.[[u]]) / 2
 template <int Nfq>
-__device__ __forceinline__ void face_flux(const double* __restrict__ T, const DevOps& ops,
-                                          const DevMesh& mesh, const double* x, int64_t e, int q,
-                                          double F[4]) {
+__device__ __forceinline__ void face_flux_at(const double* __restrict__ T, const DevOps& ops,
+                                             const DevMesh& mesh, int64_t e, int q, double n0,
+                                             double n1, double n2, double sJ, double F[4]) {
   constexpr int Nfc = 5 * Nfq;
   const int f = q / Nfq, qq = q - f * Nfq;
   const double* tm = T + (e * Nfc + q) * 4;
   const double pm = tm[0], um0 = tm[1], um1 = tm[2], um2 = tm[3];
-  double Nv[3];
-  pyr_face_normal(x, f, ops.fa[q], ops.fb[q], Nv);
-  const double sJ = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
-  const double n0 = Nv[0] / sJ, n1 = Nv[1] / sJ, n2 = Nv[2] / sJ;
   const double zm = mesh.mat[e * 4 + 2];
   const int nb = mesh.conn[e * 8 + f];
   double pp, up0, up1, up2, zp;
@@ -56,6 +53,29 @@ __device__ __forceinline__ void face_flux(const double* __restrict__ T, const De
   F[1] = n0 * Pu;
   F[2] = n1 * Pu;
   F[3] = n2 * Pu;
+}
+
+// Unit outward normal and surface Jacobian at face point q of an element
+// with vertices x: nrm = (N / |N|, |N|) for the area-weighted normal N.
+__device__ __forceinline__ void face_normal_unit(const double* x, int f, double a, double b,
+                                                 double nrm[4]) {
+  double Nv[3];
+  pyr_face_normal(x, f, a, b, Nv);
+  const double sJ = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+  nrm[0] = Nv[0] / sJ;
+  nrm[1] = Nv[1] / sJ;
+  nrm[2] = Nv[2] / sJ;
+  nrm[3] = sJ;
+}
+
+// face_flux_at with the normal computed from the element's vertices x.
+template <int Nfq>
+__device__ __forceinline__ void face_flux(const double* __restrict__ T, const DevOps& ops,
+                                          const DevMesh& mesh, const double* x, int64_t e, int q,
+                                          double F[4]) {
+  double nrm[4];
+  face_normal_unit(x, q / Nfq, ops.fa[q], ops.fb[q], nrm);
+  face_flux_at<Nfq>(T, ops, mesh, e, q, nrm[0], nrm[1], nrm[2], nrm[3], F);
 }
 
 // Ricker wavelet (1 - 2 a) exp(-a), a = (pi f0 (t - delay))^2.

@@ -290,6 +290,24 @@ struct StageWaves {
              : (FORM == 0 ? (N <= 4 ? 3 : N <= 6 ? 2 : 1) : (N <= 6 ? 3 : 2));
 };
 
+// The face normals of an element are few: the base face's vary with (a, b),
+// the four triangles are planar, so there are (N+1)^2 + 4 distinct unit
+// normals (with their surface Jacobians).  The stage kernel evaluates them
+// once per element into LDS, which saves a normal, a square root and three
+// divisions per flux evaluation, where the table keeps the workgroup within
+// 52 KiB of LDS (three workgroups per CU).  (A table of the volume metric per
+// (a, b) column, tried beside it, did not pay: measured 3.05 against 3.02 ms
+// at 384000 pyramids, N = 4.)
+template <int N, int FORM, int G>
+struct NormalTable {
+  static constexpr int EB = kWaves * kEW * G;
+  static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int base =
+      EB * 16 * 8 + kWaves * G * 16 * 17 * (FORM == 0 ? 8 : 4);  // sX, sQ
+  static constexpr int bytes = EB * (Nfq + 4) * 4 * 8;
+  static constexpr bool value = base + bytes <= 52 * 1024;
+};
+
 template <int N, int FORM, int MODE, int G>
 __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_stage_mfma(const double* __restrict__ U,
                                                        const double* __restrict__ T, FragOps fo,
@@ -300,8 +318,10 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
   using TV = typename M::T;
   constexpr int EW = kEW * G;      // elements per wave
   constexpr int EB = kWaves * EW;  // elements per workgroup
+  constexpr bool kNorm = NormalTable<N, FORM, G>::value;
   __shared__ double sX[EB][16];
   __shared__ TV sQ[kWaves][G][16][17];
+  __shared__ double sN[kNorm ? EB : 1][kNorm ? TT::Nfq + 4 : 1][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t eb0 = (int64_t)blockIdx.x * EB;
   for (int x = threadIdx.x; x < EB * 16; x += kBlock) {
@@ -313,6 +333,16 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
 #pragma unroll
   for (int g = 0; g < G; ++g) load_u_frags<N, FORM>(U, ew0 + kEW * g, mesh.K, lane, afr[g]);
   __syncthreads();
+  if (kNorm) {
+    // rows 0 .. Nfq-1: base-face points; Nfq + f - 1: triangle f = 1..4
+    for (int x = threadIdx.x; x < EB * (TT::Nfq + 4); x += kBlock) {
+      const int le = x / (TT::Nfq + 4), r = x - le * (TT::Nfq + 4);
+      const int f = r < TT::Nfq ? 0 : r - TT::Nfq + 1;
+      const int q = r < TT::Nfq ? r : f * TT::Nfq;
+      face_normal_unit(sX[le], f, ops.fa[q], ops.fb[q], sN[le][r]);
+    }
+    __syncthreads();
+  }
 
   constexpr int KP = Pack<TV>::KP;
   constexpr int NCHP = (TT::NCH + KP - 1) / KP, NITP = (TT::NIT + KP - 1) / KP;
@@ -409,8 +439,15 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
     for (int g = 0; g < G; ++g) {
       const int64_t e = ew0 + kEW * g + de;
       double F[4] = {0.0, 0.0, 0.0, 0.0};
-      if (e < mesh.K && q < TT::Nfc)
-        face_flux<TT::Nfq>(T, ops, mesh, sX[wv * EW + kEW * g + de], e, q, F);
+      if (e < mesh.K && q < TT::Nfc) {
+        if (kNorm) {
+          const int f = q / TT::Nfq;
+          const double* nr = sN[wv * EW + kEW * g + de][f == 0 ? q : TT::Nfq + f - 1];
+          face_flux_at<TT::Nfq>(T, ops, mesh, e, q, nr[0], nr[1], nr[2], nr[3], F);
+        } else {
+          face_flux<TT::Nfq>(T, ops, mesh, sX[wv * EW + kEW * g + de], e, q, F);
+        }
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) sQ[wv][g][M::row(de, v)][dq] = (TV)F[v];
     }
