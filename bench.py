@@ -400,7 +400,7 @@ def adjoint_bench(args):
     c2 = 1.0 + 0.3 * F / np.abs(F).max()
     src = [dict(x=list(rng.uniform(0.3, 0.7, 3)), f0=10.0)]
     rec = rng.uniform(0.1, 0.9, (args.adjoint_receivers, 3))
-    s = dg.Solver(xyz, e2v, N, alpha=0.0, sources=src)
+    s = dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha, sources=src)
     s.set_receivers(rec)
     U0 = s.empty_state().zero_()
     dt = s.stable_dt(0.5) / np.sqrt(c2.max())
@@ -431,7 +431,8 @@ def adjoint_bench(args):
            "n_gpus": 1, "steps": nsteps, "warmup": 0, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{args.adjoint_k1d}^3 x 6 = {K} pyramids, N={N}, c^2 = 1 + "
-                                  "0.3 F(x), central flux, walls, Ricker source, "
+                                  f"0.3 F(x), flux alpha = {args.adjoint_alpha:g}, walls, "
+                                  "Ricker source, "
                                   f"{s.nrec} receivers, {nsteps} steps, checkpoints every "
                                   f"{every}", "nelems": K, "N": N, "dof": dof, "dt": dt},
            "forward_s": t1 - t0, "gradient_s": t2 - t1, "misfit": float(J.item()),
@@ -480,6 +481,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=400)
     ap.add_argument("--adjoint-checkpoint", type=int, default=20)
     ap.add_argument("--adjoint-receivers", type=int, default=64)
+    ap.add_argument("--adjoint-alpha", type=float, default=1.0,
+                    help="flux parameter of the adjoint run (1: the flux of Section 4.3)")
     ap.add_argument("--advection", action="store_true",
                     help="advection workload (Section 4.1) instead of the bench line")
     ap.add_argument("--advection-k1d", type=int, default=64)
