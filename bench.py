@@ -380,9 +380,12 @@ def adjoint_bench(args):
     """Adjoint form: gradient of a receiver misfit with respect to per-element
     c^2 (kappa, rho = 1) through the discrete adjoint.  K1D^3 x 6 pyramids,
     c^2 = 1 + 0.3 F(x) with F a seeded sum of Fourier modes (|k|_inf <= 4,
-    max |F| = 1) at element centroids, one Ricker source (f0 = 10), seeded
-    receivers, data recorded with c^2 = 1, checkpoints every few steps.
-    Prints one JSON line with the forward and gradient times."""
+    max |F| = 1) at element centroids, one Ricker source at a seeded point
+    whose frequency fits the simulated window (f0 = 4 / T, delay 1 / f0,
+    T = steps x dt) and seeded receivers on the sphere of radius 0.3 T around
+    it (the wave passes them inside the window), data recorded with c^2 = 1,
+    checkpoints every few steps.  Prints one JSON line with the forward and
+    gradient times."""
     import torch
 
     import paper_1502_07703_amd as dg
@@ -398,13 +401,17 @@ def adjoint_bench(args):
         k = rng.integers(-4, 5, 3)
         F += rng.normal() * np.cos(2 * np.pi * (cent @ k) + rng.uniform(0, 2 * np.pi))
     c2 = 1.0 + 0.3 * F / np.abs(F).max()
-    src = [dict(x=list(rng.uniform(0.3, 0.7, 3)), f0=10.0)]
-    rec = rng.uniform(0.1, 0.9, (args.adjoint_receivers, 3))
+    nsteps, every = args.adjoint_steps, args.adjoint_checkpoint
+    with dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha) as s0:
+        dt = s0.stable_dt(0.5) / np.sqrt(c2.max())
+    T = nsteps * dt
+    xs = rng.uniform(0.4, 0.6, 3)
+    src = [dict(x=list(xs), f0=4.0 / T)]
+    d = rng.normal(size=(args.adjoint_receivers, 3))
+    rec = xs + 0.3 * T * d / np.linalg.norm(d, axis=1, keepdims=True)
     s = dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha, sources=src)
     s.set_receivers(rec)
     U0 = s.empty_state().zero_()
-    dt = s.stable_dt(0.5) / np.sqrt(c2.max())
-    nsteps, every = args.adjoint_steps, args.adjoint_checkpoint
     # data: the receiver traces of the true model c^2 = 1
     with torch.no_grad():
         s.set_kappa(np.ones(K))
@@ -432,7 +439,8 @@ def adjoint_bench(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{args.adjoint_k1d}^3 x 6 = {K} pyramids, N={N}, c^2 = 1 + "
                                   f"0.3 F(x), flux alpha = {args.adjoint_alpha:g}, walls, "
-                                  "Ricker source, "
+                                  f"Ricker source f0 = {4.0 / T:.4g}, receivers on a sphere "
+                                  f"of radius {0.3 * T:.3g} around it, "
                                   f"{s.nrec} receivers, {nsteps} steps, checkpoints every "
                                   f"{every}", "nelems": K, "N": N, "dof": dof, "dt": dt},
            "forward_s": t1 - t0, "gradient_s": t2 - t1, "misfit": float(J.item()),

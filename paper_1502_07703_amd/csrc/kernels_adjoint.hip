@@ -297,55 +297,66 @@ __global__ void k_kappa_grad(double* __restrict__ grad, const double* __restrict
 // points, s_K and the neighbour's s at the matching point (the same {rho c}
 // enters the neighbour's rows), times d{rho c}/d kappa_K = z_K / (4 kappa_K);
 // a boundary face (ghost with the element's material) gives
-// s_K z_K / (2 kappa_K).  One thread per element, no atomics.
-__global__ void k_tau_grad(double* __restrict__ grad, const double* __restrict__ TW,
-                           const double* __restrict__ TM, DevOps ops, DevMesh mesh, int Nfq,
-                           double dt) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= mesh.K) return;
+// s_K z_K / (2 kappa_K).  One wave per element, its lanes over the face
+// points, summed in a fixed order through LDS (deterministic, no atomics).
+constexpr int kTauWaves = 4;
+__global__ __launch_bounds__(64 * kTauWaves) void k_tau_grad(
+    double* __restrict__ grad, const double* __restrict__ TW, const double* __restrict__ TM,
+    DevOps ops, DevMesh mesh, int Nfq, double dt) {
+  __shared__ double sAcc[64 * kTauWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * kTauWaves + wv;
   const int Nfc = 5 * Nfq;
-  const double* x = mesh.verts + e * 16;
-  const double kap = mesh.mat[e * 4 + 0], z = mesh.mat[e * 4 + 2];
   double acc = 0.0;
-  for (int q = 0; q < Nfc; ++q) {
-    const int f = q / Nfq, qq = q - f * Nfq;
-    const double* tm = TW + (e * Nfc + q) * 4;
-    const double* mm = TM + (e * Nfc + q) * 4;
-    double Nv[3];
-    pyr_face_normal(x, f, ops.fa[q], ops.fb[q], Nv);
-    const double sJ = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
-    const double n0 = Nv[0] / sJ, n1 = Nv[1] / sJ, n2 = Nv[2] / sJ;
-    const double c = -0.5 * ops.wf[q] * sJ * mesh.alpha;
-    const double mun = n0 * mm[1] + n1 * mm[2] + n2 * mm[3];
-    const int nb = mesh.conn[e * 8 + f];
-    if (nb >= 0) {
-      const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
-      const int nf = code & 7, o = code >> 3;
-      const int pi = ops.perm[(f == 0 ? o : 8 + o) * Nfq + qq];
-      const double* tp = TW + ((int64_t)nb * Nfc + nf * Nfq + pi) * 4;
-      const double* mp = TM + ((int64_t)nb * Nfc + nf * Nfq + pi) * 4;
-      const double jp = tp[0] - tm[0];
-      const double jun = n0 * (tp[1] - tm[1]) + n1 * (tp[2] - tm[2]) + n2 * (tp[3] - tm[3]);
-      const double zavg = 0.5 * (z + mesh.mat[(int64_t)nb * 4 + 2]);
-      const double iz2 = 1.0 / (zavg * zavg);
-      const double s_own = c * (mm[0] * jp * iz2 - mun * jun);
-      const double mpn = n0 * mp[1] + n1 * mp[2] + n2 * mp[3];
-      const double s_nb = c * (-mp[0] * jp * iz2 + mpn * jun);
-      acc += (s_own + s_nb) * z / (4.0 * kap);
-    } else {
-      double jp, jun;
-      if (mesh.bc == DGPYR_BC_WALL) {
-        jp = 0.0;
-        jun = -2.0 * (n0 * tm[1] + n1 * tm[2] + n2 * tm[3]);
+  if (e < mesh.K) {
+    const double* x = mesh.verts + e * 16;
+    const double kap = mesh.mat[e * 4 + 0], z = mesh.mat[e * 4 + 2];
+    for (int q = lane; q < Nfc; q += 64) {
+      const int f = q / Nfq, qq = q - f * Nfq;
+      const double* tm = TW + (e * Nfc + q) * 4;
+      const double* mm = TM + (e * Nfc + q) * 4;
+      double Nv[3];
+      pyr_face_normal(x, f, ops.fa[q], ops.fb[q], Nv);
+      const double sJ = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+      const double n0 = Nv[0] / sJ, n1 = Nv[1] / sJ, n2 = Nv[2] / sJ;
+      const double c = -0.5 * ops.wf[q] * sJ * mesh.alpha;
+      const double mun = n0 * mm[1] + n1 * mm[2] + n2 * mm[3];
+      const int nb = mesh.conn[e * 8 + f];
+      if (nb >= 0) {
+        const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+        const int nf = code & 7, o = code >> 3;
+        const int pi = ops.perm[(f == 0 ? o : 8 + o) * Nfq + qq];
+        const double* tp = TW + ((int64_t)nb * Nfc + nf * Nfq + pi) * 4;
+        const double* mp = TM + ((int64_t)nb * Nfc + nf * Nfq + pi) * 4;
+        const double jp = tp[0] - tm[0];
+        const double jun = n0 * (tp[1] - tm[1]) + n1 * (tp[2] - tm[2]) + n2 * (tp[3] - tm[3]);
+        const double zavg = 0.5 * (z + mesh.mat[(int64_t)nb * 4 + 2]);
+        const double iz2 = 1.0 / (zavg * zavg);
+        const double s_own = c * (mm[0] * jp * iz2 - mun * jun);
+        const double mpn = n0 * mp[1] + n1 * mp[2] + n2 * mp[3];
+        const double s_nb = c * (-mp[0] * jp * iz2 + mpn * jun);
+        acc += (s_own + s_nb) * z / (4.0 * kap);
       } else {
-        jp = -2.0 * tm[0];
-        jun = 0.0;
+        double jp, jun;
+        if (mesh.bc == DGPYR_BC_WALL) {
+          jp = 0.0;
+          jun = -2.0 * (n0 * tm[1] + n1 * tm[2] + n2 * tm[3]);
+        } else {
+          jp = -2.0 * tm[0];
+          jun = 0.0;
+        }
+        const double s_own = c * (mm[0] * jp / (z * z) - mun * jun);
+        acc += s_own * z / (2.0 * kap);
       }
-      const double s_own = c * (mm[0] * jp / (z * z) - mun * jun);
-      acc += s_own * z / (2.0 * kap);
     }
   }
-  grad[e] += dt * acc;
+  sAcc[threadIdx.x] = acc;
+  __syncthreads();
+  if (lane == 0 && e < mesh.K) {
+    double sum = 0.0;
+    for (int l = 0; l < 64; ++l) sum += sAcc[wv * 64 + l];
+    grad[e] += dt * sum;
+  }
 }
 
 template <int N>
@@ -422,8 +433,9 @@ hipError_t launch_adj_post(const dgpyr_ctx& c, double* Ub, double* Rb, const dou
 
 hipError_t launch_tau_grad(const dgpyr_ctx& c, double* grad, const double* TW, const double* TM,
                            double dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_tau_grad, dim3(blocks256(c.K)), dim3(256), 0, s, grad, TW, TM, c.ops,
-                     c.mesh, c.Nfq, dt);
+  const int64_t nb = (c.K + kTauWaves - 1) / kTauWaves;
+  hipLaunchKernelGGL(k_tau_grad, dim3((unsigned)nb), dim3(64 * kTauWaves), 0, s, grad, TW, TM,
+                     c.ops, c.mesh, c.Nfq, dt);
   return hipGetLastError();
 }
 
