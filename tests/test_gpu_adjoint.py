@@ -121,13 +121,13 @@ def test_misfit_gradient_matches_oracle_discrete_adjoint():
 @pytest.mark.parametrize("alpha", [0.0, 1.0])
 def test_misfit_gradient_central_differences(alpha):
     """Gradient through the device adjoint against central differences of the
-    device misfit on seeded directions (162 pyramids, N = 3, 30 steps,
+    device misfit on 10 seeded directions (162 pyramids, N = 3, 30 steps,
     checkpoints every 10), central and penalty flux."""
     N, nsteps, dt = 3, 30, 0.01
     xyz, e2v, kap, U0, pts, data, src = _misfit_case(N, 3, nsteps, 8, 5)
     J, g = _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every=10, alpha=alpha)
     rng = np.random.default_rng(9)
-    for i in range(3):
+    for i in range(10):
         d = rng.normal(size=kap.size)
         h = 1e-4
         Jp, _ = _gpu_misfit(xyz, e2v, N, kap + h * d, U0, pts, data, src, dt, nsteps, 10, False,
