@@ -8,14 +8,51 @@
 
 namespace dgpyr {
 
+// Traces at one face point: the element's own (pm, um) and, on a face with a
+// neighbour, the neighbour's at the matching point (pp, up) with its rho c.
+struct FaceTraces {
+  double pm, um0, um1, um2;
+  double pp, up0, up1, up2, zp;
+  bool inner;
+};
+
+// Weighted flux from the traces at one face point, given the point's unit
+// outward normal n = (n0, n1, n2), w = face weight x surface Jacobian sJ and
+// the element's rho c zm.  A face without a neighbour gets the mirror state.
+// With [[a]] = a+ - a-, tau_p = alpha / {rho c}, tau_u = alpha {rho c}:
+//   F[0]   = w (n.[[u]] - tau_p [[p]]) / 2
+//   F[1+k] = w n_k ([[p]] - tau_u n.[[u]]) / 2
+__device__ __forceinline__ void flux_from_traces(const FaceTraces& t, const DevMesh& mesh,
+                                                 double zm, double n0, double n1, double n2,
+                                                 double w, double F[4]) {
+  double pp, up0, up1, up2, zp;
+  if (t.inner) {
+    pp = t.pp; up0 = t.up0; up1 = t.up1; up2 = t.up2;
+    zp = t.zp;
+  } else {
+    const double un = n0 * t.um0 + n1 * t.um1 + n2 * t.um2;
+    if (mesh.bc == DGPYR_BC_WALL) {
+      pp = t.pm; up0 = t.um0 - 2 * un * n0; up1 = t.um1 - 2 * un * n1; up2 = t.um2 - 2 * un * n2;
+    } else {
+      pp = -t.pm; up0 = t.um0; up1 = t.um1; up2 = t.um2;
+    }
+    zp = zm;
+  }
+  const double zavg = 0.5 * (zm + zp);
+  const double taup = mesh.alpha / zavg, tauu = mesh.alpha * zavg;
+  const double jp = pp - t.pm;
+  const double jun = n0 * (up0 - t.um0) + n1 * (up1 - t.um1) + n2 * (up2 - t.um2);
+  const double Pu = 0.5 * w * (jp - tauu * jun);
+  F[0] = 0.5 * w * (jun - taup * jp);
+  F[1] = n0 * Pu;
+  F[2] = n1 * Pu;
+  F[3] = n2 * Pu;
+}
+
 // Weighted flux at face point q (face f = q / Nfq) of element e, given the
-// point's unit outward normal n = (n0, n1, n2) and surface Jacobian sJ.
-// Reads the element's own trace and the neighbour's trace from T
-// ([K][Nfc][4]) through the connectivity code, or builds the mirror state on
-// a boundary face.  With [[a]] = a+ - a-, tau_p = alpha / {rho c},
-// tau_u = alpha {rho c}:
-//   F[0]   = w sJ (n.[[u]] - tau_p [[p]]) / 2
-//   F[1+k] = w sJ n_k ([[p]] - tau_u n.[[u]]) / 2
+// point's unit outward normal and surface Jacobian sJ: the element's own
+// trace and the neighbour's are read from T ([K][Nfc][4]) through the
+// connectivity code.
 template <int Nfq>
 __device__ __forceinline__ void face_flux_at(const double* __restrict__ T, const DevOps& ops,
                                              const DevMesh& mesh, int64_t e, int q, double n0,
@@ -23,36 +60,19 @@ __device__ __forceinline__ void face_flux_at(const double* __restrict__ T, const
   constexpr int Nfc = 5 * Nfq;
   const int f = q / Nfq, qq = q - f * Nfq;
   const double* tm = T + (e * Nfc + q) * 4;
-  const double pm = tm[0], um0 = tm[1], um1 = tm[2], um2 = tm[3];
-  const double zm = mesh.mat[e * 4 + 2];
+  FaceTraces t;
+  t.pm = tm[0]; t.um0 = tm[1]; t.um1 = tm[2]; t.um2 = tm[3];
   const int nb = mesh.conn[e * 8 + f];
-  double pp, up0, up1, up2, zp;
-  if (nb >= 0) {
+  t.inner = nb >= 0;
+  if (t.inner) {
     const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
     const int nf = code & 7, o = code >> 3;
     const int pi = ops.perm[(f == 0 ? o : 8 + o) * Nfq + qq];
     const double* tp = T + ((int64_t)nb * Nfc + nf * Nfq + pi) * 4;
-    pp = tp[0]; up0 = tp[1]; up1 = tp[2]; up2 = tp[3];
-    zp = mesh.mat[(int64_t)nb * 4 + 2];
-  } else {
-    const double un = n0 * um0 + n1 * um1 + n2 * um2;
-    if (mesh.bc == DGPYR_BC_WALL) {
-      pp = pm; up0 = um0 - 2 * un * n0; up1 = um1 - 2 * un * n1; up2 = um2 - 2 * un * n2;
-    } else {
-      pp = -pm; up0 = um0; up1 = um1; up2 = um2;
-    }
-    zp = zm;
+    t.pp = tp[0]; t.up0 = tp[1]; t.up1 = tp[2]; t.up2 = tp[3];
+    t.zp = mesh.mat[(int64_t)nb * 4 + 2];
   }
-  const double zavg = 0.5 * (zm + zp);
-  const double taup = mesh.alpha / zavg, tauu = mesh.alpha * zavg;
-  const double jp = pp - pm;
-  const double jun = n0 * (up0 - um0) + n1 * (up1 - um1) + n2 * (up2 - um2);
-  const double w = ops.wf[q] * sJ;
-  const double Pu = 0.5 * w * (jp - tauu * jun);
-  F[0] = 0.5 * w * (jun - taup * jp);
-  F[1] = n0 * Pu;
-  F[2] = n1 * Pu;
-  F[3] = n2 * Pu;
+  flux_from_traces(t, mesh, mesh.mat[e * 4 + 2], n0, n1, n2, ops.wf[q] * sJ, F);
 }
 
 // Unit outward normal and surface Jacobian at face point q of an element

@@ -295,17 +295,28 @@ struct StageWaves {
 // normals (with their surface Jacobians).  The stage kernel evaluates them
 // once per element into LDS, which saves a normal, a square root and three
 // divisions per flux evaluation, where the table keeps the workgroup within
-// 52 KiB of LDS (three workgroups per CU).  Measured at 384000 pyramids,
-// N = 4: 2295 instead of 2711 non-matrix vector instructions per wave, stage
-// time 3.086 against 3.092 ms.
+// 52 KiB of LDS (three workgroups per CU).  With the tables of the faces'
+// neighbours (element, matching face, permutation row, rho c) and of the
+// face-point permutations beside it, the surface loop gathers the traces of
+// tile t + 1 while tile t's flux and lift run: measured at 384000 pyramids,
+// N = 4, stage 3.09 -> 2.92 ms (N = 6, 196608 pyramids: 7.68 -> 7.38 ms) in
+// a same-device comparison.
 template <int N, int FORM, int G>
 struct NormalTable {
   static constexpr int EB = kWaves * kEW * G;
   static constexpr int Nfq = (N + 1) * (N + 1);
   static constexpr int base =
       EB * 16 * 8 + kWaves * G * 16 * 17 * (FORM == 0 ? 8 : 4);  // sX, sQ
-  static constexpr int bytes = EB * (Nfq + 4) * 4 * 8;
+  static constexpr int bytes = EB * (Nfq + 4) * 4 * 8 + EB * 5 * 24 + 10 * Nfq * 4;
   static constexpr bool value = base + bytes <= 52 * 1024;
+};
+
+// Neighbour of one element face for the trace gathers: element, offset of
+// its matching face in its trace row, row of the face-point permutation
+// table, and its rho c.
+struct FaceNb {
+  int nb, off, prow;
+  double zp;
 };
 
 template <int N, int FORM, int MODE, int G>
@@ -322,6 +333,8 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
   __shared__ double sX[EB][16];
   __shared__ TV sQ[kWaves][G][16][17];
   __shared__ double sN[kNorm ? EB : 1][kNorm ? TT::Nfq + 4 : 1][4];
+  __shared__ FaceNb sNb[kNorm ? EB : 1][5];
+  __shared__ int sPerm[kNorm ? 10 * TT::Nfq : 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t eb0 = (int64_t)blockIdx.x * EB;
   for (int x = threadIdx.x; x < EB * 16; x += kBlock) {
@@ -341,6 +354,22 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
       const int q = r < TT::Nfq ? r : f * TT::Nfq;
       face_normal_unit(sX[le], f, ops.fa[q], ops.fb[q], sN[le][r]);
     }
+    for (int x = threadIdx.x; x < EB * 5; x += kBlock) {
+      const int le = x / 5, f = x - le * 5;
+      const int64_t e = eb0 + le;
+      FaceNb fn{-1, 0, 0, 0.0};
+      if (e < mesh.K) {
+        const int nb = mesh.conn[e * 8 + f];
+        if (nb >= 0) {
+          const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+          const int nf = code & 7, o = code >> 3;
+          fn = FaceNb{nb, nf * TT::Nfq, (f == 0 ? o : 8 + o) * TT::Nfq,
+                      mesh.mat[(int64_t)nb * 4 + 2]};
+        }
+      }
+      sNb[le][f] = fn;
+    }
+    for (int x = threadIdx.x; x < 10 * TT::Nfq; x += kBlock) sPerm[x] = ops.perm[x];
     __syncthreads();
   }
 
@@ -432,9 +461,36 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
     wave_lds_sync();
   }
 
-  // surface (Algorithm 2)
+  // surface (Algorithm 2).  With the LDS tables the traces of tile t + 1 are
+  // gathered while tile t's flux and lift run.
+  auto gather = [&](int g, int q, FaceTraces& tr) {
+    const int64_t e = ew0 + kEW * g + de;
+    const int f = q / TT::Nfq, qq = q - f * TT::Nfq;
+    const double* tm = T + (e * TT::Nfc + q) * 4;
+    tr.pm = tm[0]; tr.um0 = tm[1]; tr.um1 = tm[2]; tr.um2 = tm[3];
+    const FaceNb& fn = sNb[wv * EW + kEW * g + de][f];
+    tr.inner = fn.nb >= 0;
+    if (tr.inner) {
+      const double* tp = T + ((int64_t)fn.nb * TT::Nfc + fn.off + sPerm[fn.prow + qq]) * 4;
+      tr.pp = tp[0]; tr.up0 = tp[1]; tr.up1 = tp[2]; tr.up2 = tp[3];
+      tr.zp = fn.zp;
+    }
+  };
+  FaceTraces cur[G];
+  if (kNorm) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (ew0 + kEW * g + de < mesh.K && dq < TT::Nfc) gather(g, dq, cur[g]);
+  }
+#pragma unroll
   for (int t = 0; t < TT::NTF; ++t) {
     const int q = 16 * t + dq;
+    FaceTraces nxt[G];
+    if (kNorm && t + 1 < TT::NTF) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (ew0 + kEW * g + de < mesh.K && q + 16 < TT::Nfc) gather(g, q + 16, nxt[g]);
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int64_t e = ew0 + kEW * g + de;
@@ -443,7 +499,8 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
         if (kNorm) {
           const int f = q / TT::Nfq;
           const double* nr = sN[wv * EW + kEW * g + de][f == 0 ? q : TT::Nfq + f - 1];
-          face_flux_at<TT::Nfq>(T, ops, mesh, e, q, nr[0], nr[1], nr[2], nr[3], F);
+          flux_from_traces(cur[g], mesh, mesh.mat[e * 4 + 2], nr[0], nr[1], nr[2],
+                           ops.wf[q] * nr[3], F);
         } else {
           face_flux<TT::Nfq>(T, ops, mesh, sX[wv * EW + kEW * g + de], e, q, F);
         }
@@ -467,6 +524,10 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_sta
       }
     }
     wave_lds_sync();
+    if (kNorm) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+    }
   }
 
   // inverse mass, material, RK stage (Algorithm 3)
