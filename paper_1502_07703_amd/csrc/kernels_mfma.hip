@@ -572,8 +572,10 @@ struct StagedDims {
   static constexpr int PPACKS = 4 * NITP * 64;  // packs of a projection / lift tile
   static constexpr int PACKS = 3 * DPACKS + PPACKS;
   static constexpr int BYTES = PACKS * 16;
-  // fits one workgroup's LDS next to the vertex and transpose tiles, under 64 KiB
-  static constexpr bool fits = BYTES + kEB * 16 * 8 + kWaves * 16 * 17 * 8 <= 65536;
+  // fits one workgroup's LDS next to the vertex, transpose, face-neighbour and
+  // face-point permutation tiles, under 64 KiB
+  static constexpr bool fits = BYTES + kEB * 16 * 8 + kWaves * 16 * 17 * 8 + kEB * 5 * 24 +
+                                   10 * TT::Nfq * 4 <= 65536;
 };
 
 template <int N, int FORM, int MODE>
@@ -589,12 +591,32 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, 1>::value)) void k_sta
   __shared__ double sX[kEB][16];
   __shared__ TV sQ[kWaves][16][17];
   __shared__ PV sB[SD::PACKS];  // [Dr | Ds | Dt][NCHP][64], then [4][NITP][64]
+  __shared__ FaceNb sNb[kEB][5];
+  __shared__ int sPerm[10 * TT::Nfq];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t eb0 = (int64_t)blockIdx.x * kEB;
   for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
     const int64_t e = eb0 + x / 16;
     sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
   }
+  // face neighbours and face-point permutations (visible after the first
+  // barrier of the volume loop)
+  for (int x = threadIdx.x; x < kEB * 5; x += kBlock) {
+    const int le = x / 5, f = x - le * 5;
+    const int64_t e = eb0 + le;
+    FaceNb fn{-1, 0, 0, 0.0};
+    if (e < mesh.K) {
+      const int nb = mesh.conn[e * 8 + f];
+      if (nb >= 0) {
+        const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+        const int nf = code & 7, o = code >> 3;
+        fn = FaceNb{nb, nf * TT::Nfq, (f == 0 ? o : 8 + o) * TT::Nfq,
+                    mesh.mat[(int64_t)nb * 4 + 2]};
+      }
+    }
+    sNb[le][f] = fn;
+  }
+  for (int x = threadIdx.x; x < 10 * TT::Nfq; x += kBlock) sPerm[x] = ops.perm[x];
   const int64_t ew0 = eb0 + wv * kEW;
   TV afr[TT::NCH];
   load_u_frags<N, FORM>(U, ew0, mesh.K, lane, afr);
@@ -677,11 +699,33 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, 1>::value)) void k_sta
     wave_lds_sync();
   }
 
-  // surface (Algorithm 2)
+  // surface (Algorithm 2): the traces of tile t + 1 are gathered while tile
+  // t's flux, lift staging and lift run.
+  auto gather = [&](int q, FaceTraces& tr) {
+    const int f = q / TT::Nfq, qq = q - f * TT::Nfq;
+    const double* tm = T + (e * TT::Nfc + q) * 4;
+    tr.pm = tm[0]; tr.um0 = tm[1]; tr.um1 = tm[2]; tr.um2 = tm[3];
+    const FaceNb& fn = sNb[wv * kEW + de][f];
+    tr.inner = fn.nb >= 0;
+    if (tr.inner) {
+      const double* tp = T + ((int64_t)fn.nb * TT::Nfc + fn.off + sPerm[fn.prow + qq]) * 4;
+      tr.pp = tp[0]; tr.up0 = tp[1]; tr.up1 = tp[2]; tr.up2 = tp[3];
+      tr.zp = fn.zp;
+    }
+  };
+  FaceTraces cur;
+  if (e < mesh.K && dq < TT::Nfc) gather(dq, cur);
+#pragma unroll
   for (int t = 0; t < TT::NTF; ++t) {
     const int q = 16 * t + dq;
+    FaceTraces nxt;
+    if (t + 1 < TT::NTF && e < mesh.K && q + 16 < TT::Nfc) gather(q + 16, nxt);
     double F[4] = {0.0, 0.0, 0.0, 0.0};
-    if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
+    if (e < mesh.K && q < TT::Nfc) {
+      double nr[4];
+      face_normal_unit(xv, q / TT::Nfq, ops.fa[q], ops.fb[q], nr);
+      flux_from_traces(cur, mesh, mesh.mat[e * 4 + 2], nr[0], nr[1], nr[2], ops.wf[q] * nr[3], F);
+    }
     __syncthreads();
     for (int x = threadIdx.x; x < SD::PPACKS; x += kBlock) sB[x] = LfF[(size_t)t * SD::PPACKS + x];
     __syncthreads();
@@ -699,6 +743,7 @@ __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, 1>::value)) void k_sta
       }
     }
     wave_lds_sync();
+    cur = nxt;
   }
 
   // inverse mass, material, RK stage (Algorithm 3)
