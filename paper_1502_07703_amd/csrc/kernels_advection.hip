@@ -49,29 +49,28 @@ __device__ __forceinline__ void load_adv_frags(const double* __restrict__ U, int
   }
 }
 
-// Weighted face term at face point q (face f = q / Nfq) of element e with
-// vertices x: w sJ (beta_n - alpha |beta_n|) / 2 (u+ - u-), with beta_n sJ =
-// beta . N for the area-weighted outward normal N.  u+ is the neighbour's
-// trace at the matching point, or 0 on a face without a partner.
-template <int Nfq>
-__device__ __forceinline__ double adv_flux(const double* __restrict__ T, const DevOps& ops,
-                                           const DevMesh& mesh, const AdvParams& ap,
-                                           const double* x, int64_t e, int q) {
-  constexpr int Nfc = 5 * Nfq;
-  const int f = q / Nfq, qq = q - f * Nfq;
-  const double um = T[e * Nfc + q];
+// Own and neighbour traces at one face point (up = 0 on a face without a
+// partner).
+struct AdvTraces {
+  double um, up;
+};
+
+// Neighbour of one element face: element, offset of its matching face in its
+// trace row, row of the face-point permutation table.
+struct AdvNb {
+  int nb, off, prow;
+};
+
+// Weighted face term at face point q (face f) of an element with vertices x:
+// w sJ (beta_n - alpha |beta_n|) / 2 (u+ - u-), with beta_n sJ = beta . N for
+// the area-weighted outward normal N (no square root needed).
+__device__ __forceinline__ double adv_flux_from(const AdvTraces& t, const DevOps& ops,
+                                                const AdvParams& ap, const double* x, int f,
+                                                int q) {
   double Nv[3];
   pyr_face_normal(x, f, ops.fa[q], ops.fb[q], Nv);
   const double bN = ap.beta[0] * Nv[0] + ap.beta[1] * Nv[1] + ap.beta[2] * Nv[2];
-  const int nb = mesh.conn[e * 8 + f];
-  double up = 0.0;
-  if (nb >= 0) {
-    const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
-    const int nf = code & 7, o = code >> 3;
-    const int pi = ops.perm[(f == 0 ? o : 8 + o) * Nfq + qq];
-    up = T[(int64_t)nb * Nfc + nf * Nfq + pi];
-  }
-  return 0.5 * ops.wf[q] * (bN - ap.alpha * fabs(bN)) * (up - um);
+  return 0.5 * ops.wf[q] * (bN - ap.alpha * fabs(bN)) * (t.up - t.um);
 }
 
 // Traces T[K][Nfc] = V^f u (Algorithm 3's interpolation to face points).  A
@@ -140,12 +139,29 @@ __global__ __launch_bounds__(kBlock, AdvWaves<N>::value) void k_adv_stage(
   using M = Mma<0>;
   __shared__ double sX[kEB][16];
   __shared__ double sQ[kWaves][16][17];
+  __shared__ AdvNb sNb[kEB][5];
+  __shared__ int sPerm[10 * TT::Nfq];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t eb0 = (int64_t)blockIdx.x * kEB;
   for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
     const int64_t e = eb0 + x / 16;
     sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
   }
+  for (int x = threadIdx.x; x < kEB * 5; x += kBlock) {
+    const int le = x / 5, f = x - le * 5;
+    const int64_t e = eb0 + le;
+    AdvNb fn{-1, 0, 0};
+    if (e < mesh.K) {
+      const int nb = mesh.conn[e * 8 + f];
+      if (nb >= 0) {
+        const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+        const int nf = code & 7, o = code >> 3;
+        fn = AdvNb{nb, nf * TT::Nfq, (f == 0 ? o : 8 + o) * TT::Nfq};
+      }
+    }
+    sNb[le][f] = fn;
+  }
+  for (int x = threadIdx.x; x < 10 * TT::Nfq; x += kBlock) sPerm[x] = ops.perm[x];
   const int64_t ew0 = eb0 + wv * kEW;
   double afr[TT::NCH];
   load_adv_frags<N>(U, ew0, mesh.K, lane, afr);
@@ -216,16 +232,36 @@ __global__ __launch_bounds__(kBlock, AdvWaves<N>::value) void k_adv_stage(
     wave_sync_lds();
   }
 
-  // surface
+  // surface: the traces of tile t + 1 are gathered while tile t's face terms
+  // and lift run.
+  auto gather = [&](int v, int q, AdvTraces& tr) {
+    const int le = 4 * v + de;
+    const int64_t e = ew0 + le;
+    const int f = q / TT::Nfq, qq = q - f * TT::Nfq;
+    tr.um = T[e * TT::Nfc + q];
+    const AdvNb& fn = sNb[wv * kEW + le][f];
+    tr.up = fn.nb >= 0 ? T[(int64_t)fn.nb * TT::Nfc + fn.off + sPerm[fn.prow + qq]] : 0.0;
+  };
+  AdvTraces cur[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (ew0 + 4 * v + de < mesh.K && dq < TT::Nfc) gather(v, dq, cur[v]);
+#pragma unroll
   for (int t = 0; t < TT::NTF; ++t) {
     const int q = 16 * t + dq;
+    AdvTraces nxt[4];
+    if (t + 1 < TT::NTF) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (ew0 + 4 * v + de < mesh.K && q + 16 < TT::Nfc) gather(v, q + 16, nxt[v]);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int le = 4 * v + de;
       const int64_t e = ew0 + le;
       double F = 0.0;
       if (e < mesh.K && q < TT::Nfc)
-        F = adv_flux<TT::Nfq>(T, ops, mesh, ap, sX[wv * kEW + le], e, q);
+        F = adv_flux_from(cur[v], ops, ap, sX[wv * kEW + le], q / TT::Nfq, q);
       sQ[wv][le][dq] = F;
     }
     wave_sync_lds();
@@ -241,6 +277,8 @@ __global__ __launch_bounds__(kBlock, AdvWaves<N>::value) void k_adv_stage(
       }
     }
     wave_sync_lds();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cur[v] = nxt[v];
   }
 
   // inverse mass and LSRK stage
