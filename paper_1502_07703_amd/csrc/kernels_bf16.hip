@@ -34,6 +34,13 @@ __device__ __forceinline__ void split8(const double* x, bfx8& hi, bfx8& lo) {
   }
 }
 
+// Neighbour of one element face: element, offset of its matching face in its
+// trace row, row of the face-point permutation table, its rho c.
+struct FaceNb {
+  int nb, off, prow;
+  double zp;
+};
+
 template <int N, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict__ U,
                                                        const double* __restrict__ T, Bf16Ops bo,
@@ -42,12 +49,30 @@ __global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict_
   using TT = Tiles<N>;
   __shared__ double sX[kEB][16];
   __shared__ double sQ[kWaves][16][33];
+  __shared__ FaceNb sNb[kEB][5];
+  __shared__ int sPerm[10 * TT::Nfq];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t eb0 = (int64_t)blockIdx.x * kEB;
   for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
     const int64_t e = eb0 + x / 16;
     sX[x / 16][x % 16] = e < mesh.K ? mesh.verts[e * 16 + (x % 16)] : 0.0;
   }
+  for (int x = threadIdx.x; x < kEB * 5; x += kBlock) {
+    const int le = x / 5, f = x - le * 5;
+    const int64_t e = eb0 + le;
+    FaceNb fn{-1, 0, 0, 0.0};
+    if (e < mesh.K) {
+      const int nb = mesh.conn[e * 8 + f];
+      if (nb >= 0) {
+        const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+        const int nf = code & 7, o = code >> 3;
+        fn = FaceNb{nb, nf * TT::Nfq, (f == 0 ? o : 8 + o) * TT::Nfq,
+                    mesh.mat[(int64_t)nb * 4 + 2]};
+      }
+    }
+    sNb[le][f] = fn;
+  }
+  for (int x = threadIdx.x; x < 10 * TT::Nfq; x += kBlock) sPerm[x] = ops.perm[x];
   const int64_t ew0 = eb0 + wv * kEW;
   const int row = lane & 15, kq = lane >> 4;  // A: row, 8-wide k group
   const int de = lane >> 4, dq = lane & 15;   // D: element, column
@@ -122,13 +147,44 @@ __global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict_
     __syncthreads();
   }
 
-  // surface (Algorithm 2): fluxes of 32 face points per chunk
+  // surface (Algorithm 2): fluxes of 32 face points per chunk; the traces of
+  // chunk t + 1 are gathered while chunk t's fluxes and lift run.
+  auto gather = [&](int q, FaceTraces& tr) {
+    const int f = q / TT::Nfq, qq = q - f * TT::Nfq;
+    const double* tm = T + (e * TT::Nfc + q) * 4;
+    tr.pm = tm[0]; tr.um0 = tm[1]; tr.um1 = tm[2]; tr.um2 = tm[3];
+    const FaceNb& fn = sNb[wv * kEW + de][f];
+    tr.inner = fn.nb >= 0;
+    if (tr.inner) {
+      const double* tp = T + ((int64_t)fn.nb * TT::Nfc + fn.off + sPerm[fn.prow + qq]) * 4;
+      tr.pp = tp[0]; tr.up0 = tp[1]; tr.up1 = tp[2]; tr.up2 = tp[3];
+      tr.zp = fn.zp;
+    }
+  };
+  const double zm = e < mesh.K ? mesh.mat[e * 4 + 2] : 0.0;
+  FaceTraces cur[2];
+#pragma unroll
+  for (int sub = 0; sub < 2; ++sub)
+    if (e < mesh.K && 16 * sub + dq < TT::Nfc) gather(16 * sub + dq, cur[sub]);
+#pragma unroll
   for (int t32 = 0; t32 < TT::NT32F; ++t32) {
+    FaceTraces nxt[2];
+    if (t32 + 1 < TT::NT32F) {
+#pragma unroll
+      for (int sub = 0; sub < 2; ++sub) {
+        const int q = 32 * (t32 + 1) + 16 * sub + dq;
+        if (e < mesh.K && q < TT::Nfc) gather(q, nxt[sub]);
+      }
+    }
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub) {
       const int q = 32 * t32 + 16 * sub + dq;
       double F[4] = {0.0, 0.0, 0.0, 0.0};
-      if (e < mesh.K && q < TT::Nfc) face_flux<TT::Nfq>(T, ops, mesh, xv, e, q, F);
+      if (e < mesh.K && q < TT::Nfc) {
+        double nr[4];
+        face_normal_unit(xv, q / TT::Nfq, ops.fa[q], ops.fb[q], nr);
+        flux_from_traces(cur[sub], mesh, zm, nr[0], nr[1], nr[2], ops.wf[q] * nr[3], F);
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) sQ[wv][4 * de + v][16 * sub + dq] = F[v];
     }
@@ -141,6 +197,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict_
       z[u] = mma_bf16x3(fh, fl, load_bf8(bo.LfH + fo), load_bf8(bo.LfL + fo), z[u]);
     }
     __syncthreads();
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) cur[sub] = nxt[sub];
   }
 
   // inverse mass, material, RK stage (Algorithm 3)
