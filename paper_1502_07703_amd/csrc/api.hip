@@ -132,7 +132,6 @@ struct LaunchTimer {
   }
 };
 
-// Default 4-element groups per wave of the fused matrix-core kernels.
 // Default 4-element groups per wave of the fused stage kernel.  Measured at
 // 384000 pyramids, N = 4: one group compiled for three waves per SIMD takes
 // 3.09 ms (FP64) and 2.47 ms (FP32) against 3.37 ms and 2.89 ms for two

@@ -278,16 +278,19 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 // only wave-local ordering.  In RK mode the kernel reads and writes only its
 // own elements' U and R; other workgroups read traces (T), never U, so the
 // in-place update is safe.
-// Waves per SIMD the fused stage kernel is compiled for: the largest count
-// whose register budget (512 / waves) holds the kernel without spilling
-// (checked on the gfx950 build: FP64 N = 4, one group: 150 registers for three
+// Waves per SIMD the fused stage kernel is compiled for (register budget
+// 512 / waves).  Mostly the largest count that holds the kernel without
+// spilling (gfx950 build: FP64 N = 4, one group: 150 registers for three
 // waves against 200 when unconstrained; FP64 N = 6: 236 for two waves against
-// 312).
+// 312).  FP64 N = 7 and 8 with one group spill at two waves (58 and 284
+// registers) and are still faster there than at one wave: 63.0 -> 48.4 ms
+// (N = 7, 384000 pyramids) and 66.6 -> 61.0 ms (N = 8, 196608 pyramids),
+// whereas N = 5 at three waves (38 spilled) is slower, 3.66 -> 3.92 ms.
 template <int N, int FORM, int G>
 struct StageWaves {
   static constexpr int value =
       G == 2 ? (FORM == 0 ? (N <= 4 ? 2 : 1) : (N <= 6 ? 2 : 1))
-             : (FORM == 0 ? (N <= 4 ? 3 : N <= 6 ? 2 : 1) : (N <= 6 ? 3 : 2));
+             : (FORM == 0 ? (N <= 4 ? 3 : 2) : (N <= 6 ? 3 : 2));
 };
 
 // The face normals of an element are few: the base face's vary with (a, b),
