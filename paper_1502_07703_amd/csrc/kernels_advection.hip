@@ -116,10 +116,13 @@ __global__ __launch_bounds__(kBlock) void k_adv_trace(const double* __restrict__
 }
 
 // Waves per SIMD the stage kernel is compiled for (register budget 512 /
-// waves, checked on the gfx950 build to hold the kernel without spilling).
+// waves).  Up to N = 6 the kernel fits without spilling; N = 7 and 8 spill
+// at two waves (50 and 244 registers, with the surface loop left rolled) and
+// are still faster than at one: 17.2 -> 13.9 ms and 35.2 -> 30.5 ms at
+// 40^3 x 6 periodic pyramids.
 template <int N>
 struct AdvWaves {
-  static constexpr int value = N <= 4 ? 3 : N <= 6 ? 2 : 1;
+  static constexpr int value = N <= 4 ? 3 : 2;
 };
 
 // Fused stage.  Volume (Algorithm 1): Y_rho = D_rho u at 16 cubature points
@@ -242,11 +245,14 @@ __global__ __launch_bounds__(kBlock, AdvWaves<N>::value) void k_adv_stage(
     const AdvNb& fn = sNb[wv * kEW + le][f];
     tr.up = fn.nb >= 0 ? T[(int64_t)fn.nb * TT::Nfc + fn.off + sPerm[fn.prow + qq]] : 0.0;
   };
+  // unrolled up to N = 6; above, the unrolled loop needs some 230 more
+  // registers than two waves per SIMD allow
+  constexpr int kSurfUnroll = N <= 6 ? TT::NTF : 1;
   AdvTraces cur[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
     if (ew0 + 4 * v + de < mesh.K && dq < TT::Nfc) gather(v, dq, cur[v]);
-#pragma unroll
+#pragma unroll kSurfUnroll
   for (int t = 0; t < TT::NTF; ++t) {
     const int q = 16 * t + dq;
     AdvTraces nxt[4];
