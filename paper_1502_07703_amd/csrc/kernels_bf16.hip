@@ -41,8 +41,19 @@ struct FaceNb {
   double zp;
 };
 
+// Waves per SIMD the kernel is compiled for.  Unconstrained, N >= 6 takes
+// more than 256 registers (with the accumulators) and runs one wave per
+// SIMD; at two it fits without spilling up to N = 7 (17 registers spilled at
+// N = 8) and runs 5.88 -> 3.56 ms (N = 6), 18.7 -> 12.1 ms (N = 7) and
+// 31.7 -> 24.1 ms (N = 8) at 196608 pyramids.  Below N = 6 the unconstrained
+// build already fits two or more.
+template <int N>
+struct Bf16Waves {
+  static constexpr int value = N >= 6 ? 2 : 1;
+};
+
 template <int N, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stage_bf16(const double* __restrict__ U,
+__global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(const double* __restrict__ U,
                                                        const double* __restrict__ T, Bf16Ops bo,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {
