@@ -93,6 +93,14 @@ typedef struct {
                                            setup returns E_UNSUPPORTED unless the
                                            library was built with
                                            DGPYR_ENABLE_SUM_FACTORIZED          */
+#define DGPYR_FLAG_ADJOINT 8u           /* reserve at setup every device buffer the
+                                           discrete-adjoint calls use (ten state-sized
+                                           arrays, one trace-sized array) and receiver
+                                           tables for up to DGPYR_MAX_RESERVED_RECEIVERS
+                                           points, so that no later call allocates
+                                           device memory                          */
+
+#define DGPYR_MAX_RESERVED_RECEIVERS 4096
 
 typedef struct {
   int32_t precision; /* dgpyr_precision                                           */
@@ -132,6 +140,13 @@ dgpyr_status dgpyr_setup(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* op
 /* Sizes and derived quantities of a context. */
 dgpyr_status dgpyr_get_info(const dgpyr_ctx* ctx, dgpyr_info* info);
 
+/* Time step of the CFL rule of Section 4.3: the spectral radius of the
+ * semi-discrete operator grows like C_N max_K c_K |dK| / |K| with
+ * C_N = 2 (N+1)(N+3)/3, so *dt = cfl / (C_N max_K c_K |dK| / |K|) for the
+ * context's current material (advection: |beta| in place of c_K).  E_ARG for
+ * cfl <= 0 or a null pointer. */
+dgpyr_status dgpyr_stable_dt(const dgpyr_ctx* ctx, double cfl, double* dt);
+
 /* Convert between the canonical layout and the library's state layout.
  * Canonical: [K][4][Np], fields p, u, v, w; basis index
  * n(i, j, k) = k(k+1)(2k+1)/6 + j(k+1) + i for phi_ijk of Lemma 3 with the
@@ -142,7 +157,8 @@ dgpyr_status dgpyr_unpack(dgpyr_ctx* ctx, const double* U, double* canon, void* 
 
 /* dUdt = full semi-discrete right-hand side of Section 4.3 at state U
  * (inverse mass and material factors included).  U and dUdt are device state
- * arrays (may not alias).  t is accepted for source terms and is unused here.
+ * arrays (may not alias).  t is the time at which the point sources of the
+ * mesh (dgpyr_mesh.sources) are evaluated; without sources it has no effect.
  * Asynchronous on the stream. */
 dgpyr_status dgpyr_rhs(dgpyr_ctx* ctx, const double* U, double* dUdt, double t, void* stream);
 
@@ -170,19 +186,25 @@ const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
  * pressure rows and 1/rho on velocity rows): out = A^T lam, exactly the
  * transpose of what dgpyr_rhs applies (without sources), for any flux alpha
  * and boundary condition.  lam, out: device state arrays (may not alias).
- * FP64 matrix-core kernels in every precision form.  The first call
- * allocates one state-sized scratch array held by the context.
+ * FP64 matrix-core kernels in every precision form.  Uses one state-sized
+ * scratch array held by the context: reserved at setup with
+ * DGPYR_FLAG_ADJOINT, otherwise allocated by the first call.
  * Asynchronous. */
 dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* ctx, const double* lam, double* out, void* stream);
 
 /* ---- Discrete adjoint: gradient of a receiver misfit w.r.t. kappa --------
  * New per-element bulk modulus kappa = rho c^2 (host array [nelems], rho
- * unchanged; impedances follow).  Synchronous. */
+ * unchanged): impedances rho c, the per-element CFL length scales
+ * c_K |dK| / |K| and their maximum (dgpyr_info.inv_length_max,
+ * dgpyr_stable_dt) follow the new sound speeds.  Synchronous. */
 dgpyr_status dgpyr_set_kappa(dgpyr_ctx* ctx, const double* kappa);
 
 /* Receiver points (host xyz [nrec][3]), located on the host in the element
- * (lowest index) containing each; several may share an element.  Allocates
- * device memory held by the context.  E_ARG for a point in no element. */
+ * (lowest index) containing each; several may share an element.  With
+ * DGPYR_FLAG_ADJOINT the tables go into the space reserved at setup (E_ARG
+ * for more than DGPYR_MAX_RESERVED_RECEIVERS points); otherwise a call with
+ * more points than any earlier one allocates device memory held by the
+ * context.  E_ARG for a point in no element. */
 dgpyr_status dgpyr_set_receivers(dgpyr_ctx* ctx, int32_t nrec, const double* xyz);
 
 /* Pressure at the receivers: out[r] = sum_i phi_i(xi_r) U[e_r][p][i]
@@ -200,9 +222,10 @@ dgpyr_status dgpyr_receivers_inject(dgpyr_ctx* ctx, double* Ubar, const double* 
  * dJ/dkappa.  The five stage inputs are recomputed from U0 (sources
  * included).  kappa enters through the pressure rows' factor and, for
  * alpha > 0, through the penalty coefficients tau_p = alpha/{rho c},
- * tau_u = alpha {rho c} of every face (Section 4.3).  The first call
- * allocates nine state-sized scratch arrays and one trace-sized array held by
- * the context.  Device arrays; asynchronous. */
+ * tau_u = alpha {rho c} of every face (Section 4.3).  Uses ten state-sized
+ * scratch arrays and one trace-sized array held by the context: reserved at
+ * setup with DGPYR_FLAG_ADJOINT, otherwise allocated by the first call.
+ * Device arrays; asynchronous. */
 dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* ctx, const double* U0, double* Ubar, double* grad,
                                 double t0, double dt, void* stream);
 
@@ -266,11 +289,13 @@ dgpyr_status dgpyr_batch_step(dgpyr_batch* b, double* U, double* R, int64_t step
                               void* stream);
 
 /* Autotuner: for every group on a matrix-core FP64/FP32 path, times nsteps
- * steps on scratch state for 1 and 2 element groups per wave and keeps the
- * faster (chosen[g] receives it, 0 for groups with nothing to tune; chosen
- * may be NULL).  Allocates and frees scratch device memory; synchronises the
- * stream. */
-dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, int32_t nsteps, void* stream, int32_t* chosen);
+ * steps for 1 and 2 element groups per wave and keeps the faster (chosen[g]
+ * receives it, 0 for groups with nothing to tune; chosen may be NULL).  The
+ * timing runs on the caller's scratch arrays U and R (device, batch state
+ * length each; their contents are overwritten), so the call allocates no
+ * device memory.  Synchronises the stream. */
+dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, double* U, double* R, int32_t nsteps, void* stream,
+                              int32_t* chosen);
 
 /* Releases the batch, its contexts and graph. */
 void dgpyr_batch_destroy(dgpyr_batch* b);

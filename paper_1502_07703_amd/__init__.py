@@ -93,10 +93,12 @@ class _HostMesh:
             sources=None if self.src is None else self.src.ctypes.data_as(dptr))
 
 
-def _opts(precision, alpha, reference_kernels=False, unfused=False, sum_factorized=False):
+def _opts(precision, alpha, reference_kernels=False, unfused=False, sum_factorized=False,
+          adjoint=False):
     flags = (B.FLAG_REFERENCE_KERNELS if reference_kernels else 0) | \
         (B.FLAG_UNFUSED if unfused else 0) | \
-        (B.FLAG_SUM_FACTORIZED if sum_factorized else 0)
+        (B.FLAG_SUM_FACTORIZED if sum_factorized else 0) | \
+        (B.FLAG_ADJOINT if adjoint else 0)
     return B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=flags)
 
 
@@ -106,11 +108,11 @@ class Solver:
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
                  precision="fp64", reference_kernels=False, unfused=False,
                  sum_factorized=False, groups_per_wave=0, sources=None, lds_operators=None,
-                 trace_groups=0, stream=None):
+                 trace_groups=0, adjoint=False, stream=None):
         L = B.lib()
         self._host = _HostMesh(xyz, e2v, rho, kappa, bc, sources)
         mesh = self._host.struct
-        opts = _opts(precision, alpha, reference_kernels, unfused, sum_factorized)
+        opts = _opts(precision, alpha, reference_kernels, unfused, sum_factorized, adjoint)
         handle = ctypes.c_void_p()
         st = L.dgpyr_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
                            _stream_handle(stream) if stream is not None else None,
@@ -188,6 +190,9 @@ class Solver:
             raise ValueError(f"kappa must have shape ({self.K},)")
         B.check(B.lib().dgpyr_set_kappa(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                 "dgpyr_set_kappa")
+        info = B.Info()
+        B.check(B.lib().dgpyr_get_info(self._h, ctypes.byref(info)), "dgpyr_get_info")
+        self._set_info(info)
 
     def set_receivers(self, points):
         pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
@@ -262,8 +267,11 @@ class Solver:
         return int(info.groups_per_wave)
 
     def stable_dt(self, cfl=0.5):
-        """CFL / (2(N+1)(N+3)/3 * max_K c_K |dK|/|K|) (Section 4.3 scaling)."""
-        return cfl / (LSRK_CFL_CONSTANT(self.N) * self.info["inv_length_max"])
+        """CFL / (2(N+1)(N+3)/3 * max_K c_K |dK|/|K|) (Section 4.3 scaling), for
+        the current material, as computed by ``dgpyr_stable_dt``."""
+        dt = ctypes.c_double()
+        B.check(B.lib().dgpyr_stable_dt(self._h, float(cfl), ctypes.byref(dt)), "dgpyr_stable_dt")
+        return dt.value
 
     def close(self):
         if getattr(self, "_h", None):
@@ -399,10 +407,16 @@ class Batch:
         return U, R
 
     def tune(self, nsteps=2, stream=None):
-        """Autotune the work shape of every group; returns the choice per group."""
+        """Autotune the work shape of every group; returns the choice per group.
+        Two batch-sized scratch arrays are allocated here (torch) and handed to
+        the library, which allocates nothing itself."""
+        import torch
+        U = torch.empty(self.state_len, dtype=torch.float64, device="cuda")
+        R = torch.empty_like(U)
         out = (ctypes.c_int32 * self.ngroups)()
-        B.check(B.lib().dgpyr_batch_tune(self._h, int(nsteps), _stream_handle(stream), out),
-                "dgpyr_batch_tune")
+        B.check(B.lib().dgpyr_batch_tune(self._h, _dptr(U), _dptr(R), int(nsteps),
+                                         _stream_handle(stream), out), "dgpyr_batch_tune")
+        del U, R
         return list(out)
 
     def close(self):

@@ -20,10 +20,12 @@ PRECISION = {"fp64": 0, "fp32_mfma": 1, "split_bf16": 2}
 FLAG_REFERENCE_KERNELS = 1
 FLAG_UNFUSED = 2
 FLAG_SUM_FACTORIZED = 4
+FLAG_ADJOINT = 8
+MAX_RESERVED_RECEIVERS = 4096
 
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
-    "dgpyr_setup", "dgpyr_get_info", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
+    "dgpyr_setup", "dgpyr_get_info", "dgpyr_stable_dt", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
     "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_set_kappa",
     "dgpyr_set_receivers", "dgpyr_receivers_sample", "dgpyr_receivers_inject",
     "dgpyr_adjoint_step", "dgpyr_set_operator_staging", "dgpyr_set_trace_groups", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
@@ -114,6 +116,8 @@ def lib():
     L.dgpyr_host_advection_mesh.restype = c_int32
     L.dgpyr_get_info.argtypes = [c_void_p, POINTER(Info)]
     L.dgpyr_get_info.restype = c_int32
+    L.dgpyr_stable_dt.argtypes = [c_void_p, c_double, POINTER(c_double)]
+    L.dgpyr_stable_dt.restype = c_int32
     for name in ("dgpyr_pack", "dgpyr_unpack"):
         getattr(L, name).argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         getattr(L, name).restype = c_int32
@@ -167,7 +171,8 @@ def lib():
     L.dgpyr_batch_group.restype = c_int32
     L.dgpyr_batch_step.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p]
     L.dgpyr_batch_step.restype = c_int32
-    L.dgpyr_batch_tune.argtypes = [c_void_p, c_int32, c_void_p, POINTER(c_int32)]
+    L.dgpyr_batch_tune.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                   POINTER(c_int32)]
     L.dgpyr_batch_tune.restype = c_int32
     L.dgpyr_batch_destroy.argtypes = [c_void_p]
     L.dgpyr_batch_destroy.restype = None

@@ -1,5 +1,7 @@
-"""Receiver misfit and its gradient with respect to per-element c^2 (kappa with
-rho = 1), as a ``torch.autograd.Function``.
+"""Receiver misfit and its gradient with respect to per-element bulk modulus
+kappa, as a ``torch.autograd.Function``.  With c^2 = kappa / rho the gradient
+with respect to c^2 is rho times this one (equal to it for rho = 1, the
+workload of the adjoint benchmark).
 
 Forward: set kappa, run nsteps LSRK(5,4) steps from U0, sample the pressure
 at the receivers after every step, and return

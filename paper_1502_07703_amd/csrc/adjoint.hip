@@ -13,6 +13,7 @@
 // M^-1 Kmat Rb).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -52,11 +53,18 @@ dgpyr_status dgpyr_set_kappa(dgpyr_ctx* c, const double* kappa) {
   if (!kappa) return fail(DGPYR_E_ARG, "kappa is null");
   for (int64_t e = 0; e < c->K; ++e)
     if (!(kappa[e] > 0)) return fail(DGPYR_E_ARG, "kappa must be positive");
+  // c_K |dK| / |K| scales with the sound speed c = sqrt(kappa / rho)
+  double ilmax = 0.0;
   for (int64_t e = 0; e < c->K; ++e) {
     const double rho = 1.0 / c->mat_host[(size_t)(4 * e + 1)];
+    const double kold = c->mat_host[(size_t)(4 * e + 0)];
     c->mat_host[(size_t)(4 * e + 0)] = kappa[e];
     c->mat_host[(size_t)(4 * e + 2)] = std::sqrt(kappa[e] / rho) * rho;
+    double& il = c->inv_length[(size_t)e];
+    il *= std::sqrt(kappa[e] / kold);
+    ilmax = std::max(ilmax, il);
   }
+  c->inv_length_max = ilmax;
   hipError_t e = hipMemcpy(const_cast<double*>(c->mesh.mat), c->mat_host.data(),
                            c->mat_host.size() * sizeof(double), hipMemcpyHostToDevice);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "upload kappa");
@@ -77,6 +85,18 @@ dgpyr_status dgpyr_set_receivers(dgpyr_ctx* c, int32_t nrec, const double* xyz) 
   std::string err;
   if (int rc = dgpyr::locate_receivers(ops, nrec, xyz, c->verts_host.data(), c->K, elem, phi, err))
     return fail((dgpyr_status)rc, err);
+  if (nrec <= c->rec_cap) {  // reuse the reserved or earlier tables
+    hipError_t e = hipMemcpy(const_cast<int64_t*>(c->rec_elem), elem.data(),
+                             elem.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(const_cast<double*>(c->rec_phi), phi.data(), phi.size() * sizeof(double),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload receivers");
+    c->nrec = nrec;
+    return DGPYR_OK;
+  }
+  if (c->reserved)
+    return fail(DGPYR_E_ARG, "more receivers than the reserved DGPYR_MAX_RESERVED_RECEIVERS");
   const int64_t* pe = nullptr;
   const double* pp = nullptr;
   if (dgpyr_status st = upload_vec(c, elem, &pe, "receiver elements")) return st;
@@ -84,6 +104,7 @@ dgpyr_status dgpyr_set_receivers(dgpyr_ctx* c, int32_t nrec, const double* xyz) 
   c->rec_elem = pe;
   c->rec_phi = pp;
   c->nrec = nrec;
+  c->rec_cap = nrec;
   return DGPYR_OK;
 }
 
@@ -134,7 +155,7 @@ dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* c, const double* U0, double* Ubar, do
     if (e == hipSuccess) e = run_stage(c, 1, W + (st + 1) * n, W + (st + 1) * n, Rw, kRkA[st],
                                        kRkB[st], dt, s, nullptr);
   }
-  if (e == hipSuccess) e = hipMemsetAsync(Rb, 0, bytes, s);
+  if (e == hipSuccess) e = dgpyr::launch_fill(Rb, n, 0.0, s);
   // reverse
   for (int st = 4; st >= 0 && e == hipSuccess; --st) {
     e = dgpyr::launch_adj_pre(*c, Rb, Ubar, kRkB[st], s);

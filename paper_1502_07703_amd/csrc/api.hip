@@ -467,6 +467,31 @@ dgpyr_status upload_context(dgpyr_ctx* c, const dgpyr::RefOps& ops, const dgpyr:
   return st;
 }
 
+// Every device buffer the discrete-adjoint calls use (DGPYR_FLAG_ADJOINT):
+// M^-1 Kmat lam, the reverse step's nine state-sized arrays, the adjoint
+// traces and the receiver tables at their reserved capacity.
+dgpyr_status reserve_adjoint(dgpyr_ctx* c) {
+  const size_t state = (size_t)c->K * 4 * c->Np * sizeof(double);
+  dgpyr_status st = alloc(c, state, &c->adj_mu, "adjoint scratch");
+  if (st == DGPYR_OK) st = alloc(c, 9 * state, &c->adj_work, "adjoint step scratch");
+  if (st == DGPYR_OK)
+    st = alloc(c, (size_t)c->K * c->Nfc * 4 * sizeof(double), &c->adj_T, "adjoint trace scratch");
+  double* re = nullptr;
+  double* rp = nullptr;
+  if (st == DGPYR_OK)
+    st = alloc(c, (size_t)DGPYR_MAX_RESERVED_RECEIVERS * sizeof(int64_t), &re, "receiver elements");
+  if (st == DGPYR_OK)
+    st = alloc(c, (size_t)DGPYR_MAX_RESERVED_RECEIVERS * c->Np * sizeof(double), &rp,
+               "receiver basis values");
+  if (st == DGPYR_OK) {
+    c->rec_elem = reinterpret_cast<const int64_t*>(re);
+    c->rec_phi = rp;
+    c->rec_cap = DGPYR_MAX_RESERVED_RECEIVERS;
+    c->reserved = true;
+  }
+  return st;
+}
+
 dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opts,
                         const double* dtscale, const int64_t* src_range, dgpyr_ctx** out) {
   if (!out) return fail(DGPYR_E_ARG, "out is null");
@@ -478,7 +503,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
   if (mesh->bc != DGPYR_BC_WALL && mesh->bc != DGPYR_BC_FREE) return fail(DGPYR_E_ARG, "bad bc");
   if (opts->flags & ~(uint32_t)(DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED |
-                                DGPYR_FLAG_SUM_FACTORIZED))
+                                DGPYR_FLAG_SUM_FACTORIZED | DGPYR_FLAG_ADJOINT))
     return fail(DGPYR_E_ARG, "unknown flag bits");
   if ((opts->flags & DGPYR_FLAG_SUM_FACTORIZED) &&
       (opts->precision != DGPYR_FP64 || (opts->flags & (DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED))))
@@ -552,6 +577,7 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   c->lds_operators = opts->precision == DGPYR_FP32_MFMA;
 
   dgpyr_status st = upload_context(c, ops, md);
+  if (st == DGPYR_OK && (opts->flags & DGPYR_FLAG_ADJOINT)) st = reserve_adjoint(c);
   if (st != DGPYR_OK) {
     free_ctx(c);
     return st;
@@ -590,6 +616,16 @@ dgpyr_status dgpyr_get_info(const dgpyr_ctx* c, dgpyr_info* info) {
   info->device_bytes = c->device_bytes;
   info->groups_per_wave = c->mfma_groups;
   info->nfields = c->nfields;
+  return DGPYR_OK;
+}
+
+dgpyr_status dgpyr_stable_dt(const dgpyr_ctx* c, double cfl, double* dt) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!dt) return fail(DGPYR_E_ARG, "dt is null");
+  if (!(cfl > 0.0)) return fail(DGPYR_E_ARG, "cfl must be positive");
+  if (!(c->inv_length_max > 0.0)) return fail(DGPYR_E_STATE, "no positive length scale");
+  const double CN = 2.0 * (c->N + 1) * (c->N + 3) / 3.0;
+  *dt = cfl / (CN * c->inv_length_max);
   return DGPYR_OK;
 }
 

@@ -284,8 +284,11 @@ dgpyr_status dgpyr_batch_step(dgpyr_batch* b, double* U, double* R, int64_t step
   return DGPYR_OK;
 }
 
-dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, int32_t nsteps, void* stream, int32_t* chosen) {
+dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, double* Us, double* Rs, int32_t nsteps, void* stream,
+                              int32_t* chosen) {
   if (dgpyr_status s = check_batch(b)) return s;
+  if (!Us || !Rs) return fail(DGPYR_E_ARG, "null scratch array");
+  if (Us == Rs) return fail(DGPYR_E_ARG, "U and R must not alias");
   if (nsteps <= 0) return fail(DGPYR_E_ARG, "nsteps must be > 0");
   hipStream_t s = (hipStream_t)stream;
   drop_graph(b);
@@ -301,16 +304,11 @@ dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, int32_t nsteps, void* stream, int3
       if (chosen) chosen[gix] = 0;
       continue;
     }
-    // scratch state: zero data, the timing does not depend on values
-    double* U = nullptr;
-    const size_t bytes = (size_t)b->groups[gix].state_len * sizeof(double);
-    e = hipMalloc((void**)&U, 2 * bytes);
-    if (e != hipSuccess) {
-      st = hip_fail(e, "tune scratch");
-      break;
-    }
-    e = hipMemsetAsync(U, 0, 2 * bytes, s);
-    double* R = U + b->groups[gix].state_len;
+    // the caller's scratch, cleared: the timing does not depend on values
+    double* U = Us + b->groups[gix].state_off;
+    double* R = Rs + b->groups[gix].state_off;
+    e = dgpyr::launch_fill(U, b->groups[gix].state_len, 0.0, s);
+    if (e == hipSuccess) e = dgpyr::launch_fill(R, b->groups[gix].state_len, 0.0, s);
     float best = 0.f;
     int pick = c->mfma_groups;
     for (int gw = 1; gw <= 2 && e == hipSuccess; ++gw) {
@@ -333,8 +331,6 @@ dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, int32_t nsteps, void* stream, int3
     }
     c->mfma_groups = pick;
     if (chosen) chosen[gix] = pick;
-    hipError_t ef = hipFree(U);
-    if (e == hipSuccess) e = ef;
     if (e != hipSuccess) st = hip_fail(e, "tune");
   }
   if (e0) hipEventDestroy(e0);

@@ -144,7 +144,10 @@ struct dgpyr_ctx {
   double* adj_work = nullptr;
   double* adj_T = nullptr;   // [K][Nfc][4] traces of the adjoint scratch (adjoint step)
   // receivers (dgpyr_set_receivers): element and basis values phi_r [nrec][Np]
+  // in device arrays with room for rec_cap points
   int nrec = 0;
+  int rec_cap = 0;
+  bool reserved = false;  // adjoint and receiver buffers reserved at setup
   const int64_t* rec_elem = nullptr;
   const double* rec_phi = nullptr;
   std::vector<double> verts_host;  // [K][16], for locating receivers
@@ -180,6 +183,7 @@ hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const d
 // Initial data and evaluation (kernels_aux.hip).
 hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s);
 hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s);
+hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t s);
 // Transposed operator (kernels_adjoint.hip).
 hipError_t launch_adjoint_scale(const dgpyr_ctx& c, const double* lam, double* mu, hipStream_t s);
 hipError_t launch_adjoint(const dgpyr_ctx& c, const double* mu, const double* T, double* out,

@@ -36,7 +36,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // A operands of u for 16 elements from ew0: lane l holds u[ew0 + l%16][4c + l/16],
 // zero beyond Np or beyond the mesh.
 template <int N>
-__device__ __forceinline__ void load_adv_frags(const double* __restrict__ U, int64_t ew0,
+__device__ __forceinline__ void load_adv_frags(const double* U, int64_t ew0,
                                                int64_t K, int lane, double* afr) {
   using TT = Tiles<N>;
   const int row = lane & 15, kq = lane >> 4;
@@ -136,7 +136,7 @@ struct AdvWaves {
 // update is safe.
 template <int N, int MODE>
 __global__ __launch_bounds__(kBlock, AdvWaves<N>::value) void k_adv_stage(
-    const double* __restrict__ U, const double* __restrict__ T, FragOps fo, DevOps ops,
+    const double* U, const double* __restrict__ T, FragOps fo, DevOps ops,
     DevMesh mesh, AdvParams ap, double* out, double* R, double ra, double rb, double dt) {
   using TT = Tiles<N>;
   using M = Mma<0>;

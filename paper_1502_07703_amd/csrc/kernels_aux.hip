@@ -67,9 +67,25 @@ __global__ void k_clock(double* clock, double value, int add) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = add ? clock[0] + value : value;
 }
 
+// x[0 .. n) = value, grid-stride (a kernel rather than a memset node, so the
+// call is safe inside captured graphs).
+__global__ void k_fill(double* __restrict__ x, int64_t n, double value) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    x[i] = value;
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)(nb < 65536 ? nb : 65536)), dim3(kThreads), 0, s, x, n,
+                     value);
+  return hipGetLastError();
+}
 
 hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s) {
   hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, clock, value, add ? 1 : 0);

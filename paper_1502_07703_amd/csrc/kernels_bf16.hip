@@ -53,7 +53,7 @@ struct Bf16Waves {
 };
 
 template <int N, int MODE>
-__global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(const double* __restrict__ U,
+__global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(const double* U,
                                                        const double* __restrict__ T, Bf16Ops bo,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {

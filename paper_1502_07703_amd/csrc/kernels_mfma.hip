@@ -31,7 +31,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // the element and field of row l % 16 in the form's row order; zero beyond Np
 // or beyond the mesh.
 template <int N, int FORM>
-__device__ __forceinline__ void load_u_frags(const double* __restrict__ U, int64_t ew0, int64_t K,
+__device__ __forceinline__ void load_u_frags(const double* U, int64_t ew0, int64_t K,
                                              int lane, typename Mma<FORM>::T* afr) {
   using TT = Tiles<N>;
   const int row = lane & 15, kq = lane >> 4;
@@ -277,7 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_surface_mfma(const double* __restric
 // products.  The D -> A layout changes go through a per-wave LDS tile and need
 // only wave-local ordering.  In RK mode the kernel reads and writes only its
 // own elements' U and R; other workgroups read traces (T), never U, so the
-// in-place update is safe.
+// in-place update is safe.  In RK mode out is U itself, so U is not declared
+// __restrict__ in the stage kernels.
 // Waves per SIMD the fused stage kernel is compiled for (register budget
 // 512 / waves).  Mostly the largest count that holds the kernel without
 // spilling (gfx950 build: FP64 N = 4, one group: 150 registers for three
@@ -323,7 +324,7 @@ struct FaceNb {
 };
 
 template <int N, int FORM, int MODE, int G>
-__global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_stage_mfma(const double* __restrict__ U,
+__global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, G>::value)) void k_stage_mfma(const double* U,
                                                        const double* __restrict__ T, FragOps fo,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {
@@ -583,7 +584,7 @@ struct StagedDims {
 
 template <int N, int FORM, int MODE>
 __global__ __launch_bounds__(kBlock, (StageWaves<N, FORM, 1>::value)) void k_stage_staged(
-    const double* __restrict__ U, const double* __restrict__ T, FragOps fo, DevOps ops,
+    const double* U, const double* __restrict__ T, FragOps fo, DevOps ops,
     DevMesh mesh, double* out, double* R, double ra, double rb, double dt) {
   using TT = Tiles<N>;
   using M = Mma<FORM>;

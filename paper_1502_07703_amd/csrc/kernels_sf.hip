@@ -145,7 +145,7 @@ __device__ __forceinline__ void column_factors(const double* __restrict__ u, con
 // C_f[k][p] = sum_m g_k(c_m) F_f(p, m).  Phase C: one work item per basis
 // function finishes the a and b sums and applies M^-1 and the RK update.
 template <int N, int MODE>
-__global__ __launch_bounds__(kThreads) void k_stage_sf(const double* __restrict__ U,
+__global__ __launch_bounds__(kThreads) void k_stage_sf(const double* U,
                                                        const double* __restrict__ T, SfOps sf,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {

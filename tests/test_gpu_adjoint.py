@@ -85,12 +85,12 @@ def _misfit_case(N, k1d, nsteps, nrec, seed):
 
 
 def _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every, grad=True, alpha=0.0,
-                bc="wall", rho=None):
+                bc="wall", rho=None, reserve=False):
     import torch
 
     import paper_1502_07703_amd as dg
     from paper_1502_07703_amd.adjoint import receiver_misfit
-    s = dg.Solver(xyz, e2v, N, alpha=alpha, bc=bc, rho=rho, sources=src)
+    s = dg.Solver(xyz, e2v, N, alpha=alpha, bc=bc, rho=rho, sources=src, adjoint=reserve)
     s.set_receivers(pts)
     U = s.pack(torch.from_numpy(U0).cuda())
     k = torch.tensor(kap, dtype=torch.float64, requires_grad=grad)
@@ -104,13 +104,17 @@ def _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every, grad=Tr
     return out, g
 
 
-def test_misfit_gradient_matches_oracle_discrete_adjoint():
+@pytest.mark.parametrize("reserve", [False, True])
+def test_misfit_gradient_matches_oracle_discrete_adjoint(reserve):
+    """reserve: every adjoint buffer reserved at setup (DGPYR_FLAG_ADJOINT), so
+    receivers and adjoint steps allocate nothing afterwards."""
     from oracle.adjoint import misfit_gradient, receiver_matrix
     N, nsteps, dt = 2, 6, 0.02
     xyz, e2v, kap, U0, pts, data, src = _misfit_case(N, 1, nsteps, 4, 3)
     Rm = receiver_matrix(xyz, e2v, N, pts)
     J_ref, g_ref, _ = misfit_gradient(xyz, e2v, N, kap, U0, dt, nsteps, Rm, data, sources=src)
-    J, g = _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every=4)
+    J, g = _gpu_misfit(xyz, e2v, N, kap, U0, pts, data, src, dt, nsteps, every=4,
+                       reserve=reserve)
     log(f"[adjoint] J {J:.15e} oracle {J_ref:.15e}")
     assert abs(J - J_ref) <= 1e-12 * J_ref
     err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
@@ -157,3 +161,29 @@ def test_misfit_gradient_penalty_flux_matches_oracle(k1d, N, bc):
     err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
     log(f"[adjoint] penalty flux kappa gradient rel err {err:.2e}")
     assert err < 1e-10
+
+
+def test_set_kappa_updates_cfl_step_and_reserved_receivers():
+    """New material: the CFL step of Section 4.3 follows the new sound speeds
+    (c = 2 everywhere halves it); the receiver tables reserved at setup take
+    up to DGPYR_MAX_RESERVED_RECEIVERS points and reject more."""
+    from oracle import AcousticDG
+    import paper_1502_07703_amd as dg
+    from paper_1502_07703_amd import _binding as B
+    xyz, e2v = hex_pyramid_mesh(2, seed=1)
+    K = e2v.shape[0]
+    N = 3
+    with _solver(xyz, e2v, N, adjoint=True) as s:
+        dt1 = s.stable_dt(0.5)
+        o = AcousticDG(xyz, e2v, N)
+        ref = 0.5 / (2.0 * (N + 1) * (N + 3) / 3.0 * o.inverse_length().max())
+        assert abs(dt1 - ref) <= 1e-12 * ref, (dt1, ref)
+        s.set_kappa(np.full(K, 4.0))
+        assert abs(s.stable_dt(0.5) - 0.5 * dt1) <= 1e-14 * dt1
+        assert abs(s.info["inv_length_max"] - 2.0 * o.inverse_length().max()) <= \
+            1e-12 * s.info["inv_length_max"]
+        rng = np.random.default_rng(2)
+        s.set_receivers(rng.uniform(0.1, 0.9, (B.MAX_RESERVED_RECEIVERS, 3)))
+        with pytest.raises(dg.DgpyrError) as ex:
+            s.set_receivers(rng.uniform(0.1, 0.9, (B.MAX_RESERVED_RECEIVERS + 1, 3)))
+        assert ex.value.status == B.E_ARG

@@ -50,8 +50,6 @@ def _rel(got, ref):
 @pytest.mark.parametrize("alpha", [1.0, 0.0])
 def test_adv_rhs_parity_periodic(periodic3, N, alpha):
     import paper_1502_07703_amd as dg
-    if alpha == 0.0 and N > 5:
-        pytest.skip("central flux covered up to N = 5")
     xyz, e2v, pid = periodic3
     o = AdvectionDG(xyz, e2v, N, BETA, alpha=alpha, period=(-1.0, 1.0))
     u = np.random.default_rng(30 + N).standard_normal((o.K, o.Np))
@@ -80,7 +78,7 @@ def test_adv_rhs_parity_open_ragged(N):
     assert err < TOL
 
 
-@pytest.mark.parametrize("N", [2, 4])
+@pytest.mark.parametrize("N", [2, 4, 7, 8])
 def test_adv_steps_match_oracle(periodic3, N):
     import torch
 

@@ -121,13 +121,24 @@ def test_energy_on_gpu(alpha):
         assert np.all(np.diff(E) < 0.0)
 
 
-@pytest.mark.parametrize("N,m", [(3, 2), (5, 3)])
+# Error floor of the split-BF16 form on this run (about 100 RK stages): each
+# split operand keeps about 16 mantissa bits and the FP32 accumulation adds
+# its own rounding, so the discrete solution carries an error of a few 1e-6
+# whatever the mode (the 64^3 x 6 study measures 1e-6 to 3e-6 after 100
+# steps).  FP32-MFMA's floor is about 2e-8.
+SPLIT_BF16_FLOOR = 3e-6
+FP32_FLOOR = 5e-8
+
+
+@pytest.mark.parametrize("N,m", [(3, 2), (5, 2), (5, 3)])
 def test_fp32_form_error_against_standing_wave(N, m):
     """Both precision forms against the exact standing wave (mode m) after the
-    same run: equal L2 error (within 10 % of the FP64 error) where the FP64
-    error is above the single-precision floor.  The mode number m is the knob
-    that keeps it there: at N = 5, m = 2 on this mesh the FP64 error (8.5e-6)
-    is already at the split-BF16 floor (its error was 20 % larger)."""
+    same run.  Equal L2 error means within 10 % of the FP64 error; a form
+    reaches it only where the FP64 error is well above the form's floor, so
+    each form must be within max(10 % of the FP64 error, its floor).  At
+    N = 5, m = 2 on this mesh the FP64 error (about 8.5e-6) is only a few
+    times the split-BF16 floor: there split-BF16 is not at equal error and is
+    held to its floor; at m = 3 it is at equal error."""
     import paper_1502_07703_amd as dg
     k1d, T = 4, 0.1
     xyz, e2v = hex_pyramid_mesh(k1d, seed=9)
@@ -139,7 +150,12 @@ def test_fp32_form_error_against_standing_wave(N, m):
             n = int(np.ceil(T / s.stable_dt(0.5)))
             s.step(U, R, T / n, n)
             errs[prec] = _l2_error(s, U, m, T, P, wJ)
-    log(f"[physics] N={N} L2 errors {errs}")
-    for prec in ("fp32_mfma", "split_bf16"):
-        rel = abs(errs[prec] - errs["fp64"]) / errs["fp64"]
-        assert rel < 0.1, errs
+    log(f"[physics] N={N} m={m} L2 errors {errs}")
+    e64 = errs["fp64"]
+    for prec, floor in (("fp32_mfma", FP32_FLOOR), ("split_bf16", SPLIT_BF16_FLOOR)):
+        assert abs(errs[prec] - e64) <= max(0.1 * e64, floor), (prec, errs)
+    assert abs(errs["fp32_mfma"] - e64) <= 0.1 * e64, errs  # FP32 at equal error here
+    if (N, m) != (5, 2):
+        assert abs(errs["split_bf16"] - e64) <= 0.1 * e64, errs
+
+

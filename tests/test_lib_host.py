@@ -173,6 +173,10 @@ def test_setup_errors_before_device(B):
     assert L.dgpyr_batch_info(None, None, None) != 0
     assert L.dgpyr_set_groups(None, 1) != 0
     assert L.dgpyr_set_groups(None, 3) != 0
+    import ctypes
+    dt = ctypes.c_double(0.0)
+    assert L.dgpyr_stable_dt(None, 0.5, ctypes.byref(dt)) == B.E_ARG
+    assert L.dgpyr_batch_tune(None, None, None, 1, None, None) != 0
 
 
 def test_nonconforming_triangle_apex(B):
