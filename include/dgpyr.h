@@ -192,6 +192,23 @@ const char* dgpyr_kernel_names(const dgpyr_ctx* ctx);
  * Asynchronous. */
 dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* ctx, const double* lam, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result
+ * as dgpyr_adjoint_rhs, with its state-sized scratch (M^-1 Kmat lam) in a
+ * static device array of DGPYR_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends (its address is looked up once
+ * per device by dgpyr_setup).  The call allocates nothing and calls no
+ * allocating routine; the traces go to the context's trace buffer, as in
+ * dgpyr_adjoint_rhs.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (every entry the call reads it writes
+ * first): calls that overlap in time on one GPU race, so serialise them (one
+ * stream, or events).  Errors: E_ARG when 4 K Np doubles exceed the array
+ * (then nothing is launched), null or aliasing arrays; E_UNSUPPORTED on an
+ * advection context.  Asynchronous. */
+#define DGPYR_NOALLOC_SCRATCH_BYTES (64u << 20)
+dgpyr_status dgpyr_adjoint_rhs_noalloc(dgpyr_ctx* ctx, const double* lam, double* out,
+                                       void* stream);
+
 /* ---- Discrete adjoint: gradient of a receiver misfit w.r.t. kappa --------
  * New per-element bulk modulus kappa = rho c^2 (host array [nelems], rho
  * unchanged): impedances rho c, the per-element CFL length scales

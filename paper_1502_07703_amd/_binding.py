@@ -22,11 +22,13 @@ FLAG_UNFUSED = 2
 FLAG_SUM_FACTORIZED = 4
 FLAG_ADJOINT = 8
 MAX_RESERVED_RECEIVERS = 4096
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_stable_dt", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
-    "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_set_kappa",
+    "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_adjoint_rhs_noalloc",
+    "dgpyr_set_kappa",
     "dgpyr_set_receivers", "dgpyr_receivers_sample", "dgpyr_receivers_inject",
     "dgpyr_adjoint_step", "dgpyr_set_operator_staging", "dgpyr_set_trace_groups", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
     "dgpyr_host_mesh", "dgpyr_host_sources", "dgpyr_volume_points", "dgpyr_project", "dgpyr_eval",
@@ -130,6 +132,8 @@ def lib():
     L.dgpyr_step_timed.restype = c_int32
     L.dgpyr_adjoint_rhs.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     L.dgpyr_adjoint_rhs.restype = c_int32
+    L.dgpyr_adjoint_rhs_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    L.dgpyr_adjoint_rhs_noalloc.restype = c_int32
     L.dgpyr_set_kappa.argtypes = [c_void_p, POINTER(c_double)]
     L.dgpyr_set_kappa.restype = c_int32
     L.dgpyr_set_receivers.argtypes = [c_void_p, c_int32, POINTER(c_double)]

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -14,10 +15,43 @@
 #include "host/refops.hpp"
 #include "internal.hpp"
 
+// Scratch of dgpyr_adjoint_rhs_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes the name
+// `scratch` to a kernel or copy (on the host it is only a stand-in for the
+// symbol); it uses the per-device address that set-up obtains from
+// hipGetSymbolAddress with that device current.
+constexpr size_t kScratchDoubles = DGPYR_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace dgpyr {
 namespace api {
 
 thread_local std::string g_err;
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` per device
+}  // namespace
+
+// Looks up the address of `scratch` on the current device (once per device).
+dgpyr_status scratch_for_current_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(DGPYR_E_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return DGPYR_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!p) return fail(DGPYR_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_ptr[dev] = static_cast<double*>(p);
+  return DGPYR_OK;
+}
+
+double* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 dgpyr_status fail(dgpyr_status s, const std::string& msg) {
   g_err = msg;
@@ -576,7 +610,11 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   // N = 5 at 196608 pyramids: 3.84 -> 4.64 ms), so it is on for FP32 only.
   c->lds_operators = opts->precision == DGPYR_FP32_MFMA;
 
-  dgpyr_status st = upload_context(c, ops, md);
+  // first device work: the device of the context and its static scratch
+  hipError_t ed = hipGetDevice(&c->device);
+  dgpyr_status st = ed == hipSuccess ? scratch_for_current_device(c->device)
+                                     : hip_fail(ed, "hipGetDevice");
+  if (st == DGPYR_OK) st = upload_context(c, ops, md);
   if (st == DGPYR_OK && (opts->flags & DGPYR_FLAG_ADJOINT)) st = reserve_adjoint(c);
   if (st != DGPYR_OK) {
     free_ctx(c);
@@ -729,6 +767,25 @@ dgpyr_status dgpyr_adjoint_rhs(dgpyr_ctx* c, const double* lam, double* out, voi
   hipError_t e = dgpyr::launch_adjoint_scale(*c, lam, c->adj_mu, s);
   if (e == hipSuccess) e = dgpyr::launch_trace_mfma(*c, c->adj_mu, c->T, s);
   if (e == hipSuccess) e = dgpyr::launch_adjoint(*c, c->adj_mu, c->T, out, s);
+  return e == hipSuccess ? DGPYR_OK : hip_fail(e, "adjoint launch");
+}
+
+dgpyr_status dgpyr_adjoint_rhs_noalloc(dgpyr_ctx* c, const double* lam, double* out,
+                                       void* stream) {
+  if (dgpyr_status s = check_acoustic(c)) return s;
+  if (!lam || !out) return fail(DGPYR_E_ARG, "null array");
+  if ((const double*)out == lam) return fail(DGPYR_E_ARG, "lam and out must not alias");
+  const size_t need = (size_t)c->K * 4 * c->Np;
+  if (need > kScratchDoubles)
+    return fail(DGPYR_E_ARG, "state of " + std::to_string(need * sizeof(double)) +
+                                 " bytes exceeds the static scratch of " +
+                                 std::to_string(DGPYR_NOALLOC_SCRATCH_BYTES) + " bytes");
+  double* mu = scratch_ptr(c->device);
+  if (!mu) return fail(DGPYR_E_STATE, "static scratch not set up on the context's device");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = dgpyr::launch_adjoint_scale(*c, lam, mu, s);
+  if (e == hipSuccess) e = dgpyr::launch_trace_mfma(*c, mu, c->T, s);
+  if (e == hipSuccess) e = dgpyr::launch_adjoint(*c, mu, c->T, out, s);
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "adjoint launch");
 }
 

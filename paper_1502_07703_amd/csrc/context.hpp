@@ -165,6 +165,7 @@ struct dgpyr_ctx {
   double* clock = nullptr;  // device step counter (source times)
   int nsrc = 0;
   int64_t device_bytes = 0;
+  int device = 0;  // HIP device the context was set up on
   std::vector<void*> allocs;
   // host copies kept for batches (per-problem time steps): c_K |dK| / |K| and
   // the material rows [K][4] whose last entry scales the time step
