@@ -3,16 +3,20 @@
 
 One bench step is one LSRK(5,4) time step: five stages, each a full
 right-hand side (trace, volume, surface + lift, inverse mass) and the RK
-update, over every element of the mesh.  Default workload: the unit cube as
-40^3 perturbed hexahedra x 6 = 384 000 pyramids, N = 4 (Np = 55), four fields,
-c = 1, wall boundaries, penalty flux; synthetic seeded mesh; initial data the
-L2-projected wall eigenmode cos(pi x) cos(pi y) cos(pi z); 200 timed steps.
+update, over every element of the mesh.  Default workload (the precision-form
+configuration): the unit cube as 64^3 perturbed hexahedra x 6 = 1 572 864
+pyramids (seed 3), N = 5 (Np = 91), four fields, c = 1, wall boundaries,
+penalty flux; initial data the L2-projected wall eigenmode of number m, with
+m chosen per N so that the FP64 error lies above the single-precision floors
+(equal-error comparison, Section 4.3); then the same for N = 6 and 7.
 
-Prints one JSON line.  ``value`` is GDOF.stages/s = 4 Np K * 5 * steps / t for
-the FP64 path.  The same line carries the L2 error against the exact mode at
-the final time and, for the FP32-MFMA and split-BF16 forms run on the same
-workload, initial data and step count, their throughput, speedup and L2
-errors (equal error: within 10 % of the FP64 error).
+Prints one JSON line.  ``value`` is GDOF.stages/s = 4 Np K * 5 * steps / t of
+the FP64 path at the headline N; the line carries for FP64 and for the
+FP32-MFMA and split-BF16 forms their throughput, roofline (FP64 and FP32
+against their matrix-core peaks, split-BF16 against HBM), L2 error against the
+exact mode and whether the form is at equal error (within 10 % of the FP64
+error), and the CPU oracle's throughput on all host cores (at most 16) and on
+one.
 """
 
 from __future__ import annotations
@@ -60,6 +64,33 @@ def kernel_work(name: str, N: int):
         return (32 * Nc * Np + 40 * Nc + 8 * Nfc * Np + 25 * Nfc + 24 * Np,
                 32 * Np * 4 + 32 * Nab + 152)
     raise KeyError(name)
+
+
+def sf_work(name: str, N: int, local: bool = True):
+    """Flops and HBM bytes per element of one launch of a sum-factorised
+    kernel: the multiply-adds of its one-dimensional contractions (a-, b- and
+    c-directions), pointwise metric and fluxes, and the FP64 data it must move
+    with traces kept as (p, u.n) pairs -- base faces only when whole
+    hexahedra share a workgroup (local), all five faces otherwise."""
+    n1 = N + 1
+    n2, Np, KJ = n1 * n1, n_basis(N), n1 * (n1 + 1) // 2
+    if name == "trace":
+        fma = 4 * n1 * (Np + KJ + n1 * KJ)
+        if not local:
+            fma += 16 * n1 * (Np + KJ + n2)
+        return 2 * fma, 32 * Np + (16 if local else 80) * n2
+    if name == "stage":
+        per_field = (2 * n1 * Np + 4 * n1 * (Np + KJ + n2) + n2 * (3 * KJ + 3 * n2 + 3 * n1)
+                     + KJ * n2 + 5 * n1 * Np)
+        fma = (4 * per_field + n2 * (9 * n1 + 3 * n2) + 3 * n2 * n1 + n2 * (n2 + 4 * n1)
+               + 8 * n1 * n2)
+        return 2 * fma, 128 * Np + (16 if local else 80) * n2 + 152
+    raise KeyError(name)
+
+
+def work(name: str, N: int, path: str = "fused"):
+    """Per-element work of one launch of kernel ``name`` on kernel path ``path``."""
+    return sf_work(name, N) if path == "sumfact" else kernel_work(name, N)
 
 
 def stage_work(N: int):
@@ -141,26 +172,91 @@ def l2_norm(solver, U, P, wJ, mode=None, chunk=65536):
     return float(np.sqrt(tot))
 
 
-def cpu_baseline(xyz, e2v, N, U, nsample, reps=3):
-    """The oracle's right-hand side on a seeded sample of elements, one thread."""
+def _host_model():
+    """CPU model name of this host (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _host_cores():
+    """Cores this process may use, capped at 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _face_closure(xyz, e2v, S):
+    """Sub-mesh of the sample S and every element sharing three or more
+    vertices with the sample's vertex set (a superset of the face
+    neighbours): returns (xyz_sub, e2v_sub, local ids of S, global ids)."""
+    Vs = np.unique(e2v[S])
+    cnt = np.isin(e2v, Vs).sum(axis=1)
+    sub = np.union1d(S, np.nonzero(cnt >= 3)[0])
+    uniq, inv = np.unique(e2v[sub], return_inverse=True)
+    return xyz[uniq], inv.reshape(-1, 5).astype(np.int64), np.searchsorted(sub, S), sub
+
+
+def _oracle_worker(args):
+    """One worker of the CPU baseline: the oracle's right-hand side on its
+    sample of elements (BLAS limited to one thread), timed after a barrier so
+    that all workers run at once.  Returns (dof, median seconds)."""
+    xyz, e2v, N, loc, U, reps, barrier, queue = args
     from threadpoolctl import threadpool_limits
 
     from oracle import AcousticDG
-    K = e2v.shape[0]
-    rng = np.random.default_rng(2024)
-    S = np.sort(rng.choice(K, min(nsample, K), replace=False))
-    o = AcousticDG(xyz, e2v, N, elems=S)
-    times = []
     with threadpool_limits(1):
+        o = AcousticDG(xyz, e2v, N, elems=loc)
+        o.rhs(U)  # warm-up
+        if barrier is not None:
+            barrier.wait()
+        times = []
         for _ in range(reps):
             t0 = time.perf_counter()
             o.rhs(U)
             times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    rate = 4 * n_basis(N) * S.size / t / 1e9
-    return {"value": rate, "unit": "GDOF·stages/s", "cores": 1, "kind": "oracle",
-            "sample": f"{S.size} of {K} elements, one right-hand side (= one stage), median of "
-                      f"{reps}, BLAS limited to 1 thread, host {platform.processor() or platform.machine()}"}
+    queue.put((4 * n_basis(N) * loc.size, float(np.median(times))))
+
+
+def cpu_baseline(xyz, e2v, N, per_worker, workers, reps=3, seed=2024):
+    """The oracle (test infrastructure, as it stands) timed on this host's
+    cores: ``workers`` processes, each evaluating one right-hand side on its
+    own seeded sample of ``per_worker`` elements (plus their face neighbours
+    as context), ``reps`` times after a common barrier.  Throughput is the workers' total
+    DOF over the slowest worker's median time (they run concurrently).  Runs
+    in fresh processes (spawn) before this process touches the GPU."""
+    import multiprocessing as mp
+    from synth import random_state
+    K = e2v.shape[0]
+    rng = np.random.default_rng(seed)
+    S_all = rng.choice(K, min(per_worker * workers, K), replace=False)
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(workers) if workers > 1 else None
+    queue = ctx.Queue()
+    procs = []
+    for w in range(workers):
+        S = np.sort(S_all[w::workers])
+        xs, es, loc, sub = _face_closure(xyz, e2v, S)
+        U = random_state(es.shape[0], N, seed=seed + w)
+        p = ctx.Process(target=_oracle_worker, args=((xs, es, N, loc, U, reps, barrier, queue),))
+        p.start()
+        procs.append(p)
+    res = [queue.get() for _ in procs]
+    for p in procs:
+        p.join()
+    dof = sum(r[0] for r in res)
+    t = max(r[1] for r in res)
+    return {"value": dof / t / 1e9, "unit": "GDOF·stages/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} x {per_worker} of {K} elements (seeded), one right-hand side "
+                      f"(= one stage) each, concurrently, median of {reps}; BLAS 1 thread per "
+                      f"process; host: {_host_model()}, {os.cpu_count()} CPUs visible"}
 
 
 def timed_steps(dg, solver, U, R, t0, dt, nsteps, stream):
@@ -402,14 +498,15 @@ def adjoint_bench(args):
         F += rng.normal() * np.cos(2 * np.pi * (cent @ k) + rng.uniform(0, 2 * np.pi))
     c2 = 1.0 + 0.3 * F / np.abs(F).max()
     nsteps, every = args.adjoint_steps, args.adjoint_checkpoint
-    with dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha) as s0:
-        dt = s0.stable_dt(0.5) / np.sqrt(c2.max())
+    # the CFL step of the model c^2 (the larger sound speed: stable for c = 1 too)
+    with dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha, kappa=c2) as s0:
+        dt = s0.stable_dt(0.5)
     T = nsteps * dt
     xs = rng.uniform(0.4, 0.6, 3)
     src = [dict(x=list(xs), f0=4.0 / T)]
     d = rng.normal(size=(args.adjoint_receivers, 3))
     rec = xs + 0.3 * T * d / np.linalg.norm(d, axis=1, keepdims=True)
-    s = dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha, sources=src)
+    s = dg.Solver(xyz, e2v, N, alpha=args.adjoint_alpha, sources=src, adjoint=True)
     s.set_receivers(rec)
     U0 = s.empty_state().zero_()
     # data: the receiver traces of the true model c^2 = 1
@@ -433,6 +530,21 @@ def adjoint_bench(args):
     g = kap.grad.numpy()
     Np = n_basis(N)
     dof = 4 * Np * K
+    # central differences of the misfit on seeded directions (forward runs only)
+    fd = []
+    rng_d = np.random.default_rng(5100)
+    for i in range(args.adjoint_fd_directions):
+        d = rng_d.normal(size=K)
+        h = 1e-4
+        with torch.no_grad():
+            Jp = float(receiver_misfit(torch.tensor(c2 + h * d), s, U0, data, dt, nsteps,
+                                       every).item())
+            Jm = float(receiver_misfit(torch.tensor(c2 - h * d), s, U0, data, dt, nsteps,
+                                       every).item())
+        fdv, adv = (Jp - Jm) / (2 * h), float(g @ d)
+        fd.append({"fd": fdv, "adjoint": adv, "rel_diff": abs(fdv - adv) / abs(fdv)})
+        print(f"[adjoint] direction {i}: fd {fdv:.12e} adjoint {adv:.12e}", file=sys.stderr,
+              flush=True)
     out = {"metric": "gradient of a receiver misfit w.r.t. per-element c^2 (discrete adjoint)",
            "value": dof * 5 * nsteps / (t2 - t0) / 1e9, "unit": "GDOF·stages/s of forward run",
            "n_gpus": 1, "steps": nsteps, "warmup": 0, "higher_is_better": True,
@@ -444,19 +556,143 @@ def adjoint_bench(args):
                                   f"{s.nrec} receivers, {nsteps} steps, checkpoints every "
                                   f"{every}", "nelems": K, "N": N, "dof": dof, "dt": dt},
            "forward_s": t1 - t0, "gradient_s": t2 - t1, "misfit": float(J.item()),
-           "gradient_norm": float(np.linalg.norm(g)), "gradient_finite": bool(np.isfinite(g).all())}
+           "gradient_norm": float(np.linalg.norm(g)), "gradient_finite": bool(np.isfinite(g).all()),
+           "central_differences": {"h": 1e-4, "directions": fd,
+                                   "max_rel_diff": max((x["rel_diff"] for x in fd), default=None)}}
     s.close()
     print(json.dumps(out), flush=True)
+
+
+FORM_PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32_mfma": PEAK_FP32_TFLOPS}
+FORM_DTYPE = {"fp64": "f64", "fp32_mfma": "f32 contractions, f64 state",
+              "split_bf16": "bf16x3 contractions, f64 state"}
+# Wall-eigenmode number per N at which every form reaches equal L2 error on the
+# 64^3 x 6 mesh (the FP64 error lies well above the FP32 and split-BF16 floors;
+# measured with --study: N = 5, m = 32: 9.1e-6; N = 6, m = 48: 1.1e-5;
+# N = 7, m = 64: 7.0e-6, all three forms within 10 %).
+EQUAL_ERROR_MODE = {3: 16, 4: 32, 5: 32, 6: 48, 7: 64}
+
+
+def roofline(kernel, N, K, avg_ms, form, path, traffic):
+    """Roofline object of one kernel: algorithmic flops (or bytes) per launch
+    over its average HIP-event duration, against the peak that binds it.
+    FP64 and FP32 contraction kernels: their matrix-core peak (compute-bound at
+    these orders); split-BF16: HBM, since its three bf16 products per
+    multiply-add take less time at the bf16 peak than its bytes at 8 TB/s;
+    the sum-factorised FP64 stage: whichever of its vector-ALU flops at the
+    FP64 peak and its bytes at 8 TB/s takes longer."""
+    F, Bb = work(kernel, N, path)
+    t = avg_ms * 1e-3
+    per = {"flop": F * K, "bytes": Bb * K}
+    compute_bound = F / (PEAK_FP64_TFLOPS * 1e12) >= Bb / (PEAK_HBM_GBS * 1e9)
+    if form == "split_bf16" or not compute_bound:
+        ach = Bb * K / t / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "kernel": kernel,
+                "per_launch": per}
+    ach = F * K / t / 1e12
+    peak = FORM_PEAK[form]
+    return {"bound": "mfma" if path in ("fused", "unfused") else "alu", "achieved": ach,
+            "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
+            "kernel": kernel, "per_launch": per}
+
+
+def run_form(dg, xyz, e2v, k1d, N, form, mode, steps, warmup, stream, path="fused", groups=0,
+             trace_groups=0, lds_operators=None, keep_state=False):
+    """One precision form / kernel path on one mesh: projected wall mode m,
+    ``warmup`` untimed steps, ``steps`` timed steps (dgpyr_step_timed), L2 error
+    against the exact mode at the final time.  Returns a result dict (and the
+    final state and the cubature points when keep_state)."""
+    import torch
+    K = e2v.shape[0]
+    Np = n_basis(N)
+    print(f"[bench] N={N} {form} {path} K={K} m={mode}", file=sys.stderr, flush=True)
+    t_setup = time.perf_counter()
+    s = dg.Solver(xyz, e2v, N, precision=form, reference_kernels=path == "reference",
+                  unfused=path == "unfused", sum_factorized=path == "sumfact",
+                  groups_per_wave=groups, trace_groups=trace_groups, lds_operators=lds_operators)
+    t_setup = time.perf_counter() - t_setup
+    P, wJ = s.volume_points()
+    U = s.project(wall_mode_values(P, mode, 0.0))
+    R = s.empty_state().zero_()
+    dt = s.stable_dt(0.5)
+    s.step(U, R, dt, warmup)
+    torch.cuda.synchronize()
+    wall, names, ms, cnt = timed_steps(dg, s, U, R, warmup * dt, dt, steps, stream)
+    if not torch.isfinite(U).all():
+        print(f"non-finite state after the timed steps ({form}, N={N})", file=sys.stderr)
+        sys.exit(1)
+    stages = 5 * steps
+    kernels = {}
+    for i, nm in enumerate(names):
+        avg = ms[i] / max(cnt[i], 1)
+        F, Bb = work(nm, N, path)
+        kernels[nm] = {"avg_ms": avg, "launches": int(cnt[i]),
+                       "tflops": F * K / (avg * 1e-3) / 1e12,
+                       "gbs": Bb * K / (avg * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    g = s.info_groups()
+    traffic = recorded_traffic(dom, f"k1d={k1d} N={N} {form} {path} g{g}")
+    T_end = (warmup + steps) * dt
+    res = {"value": 4 * Np * K * stages / wall / 1e9, "ms_per_step": wall / steps * 1e3,
+           "dt": dt, "t_end": T_end, "setup_s": t_setup, "groups_per_wave": g,
+           "l2_error_vs_mode": l2_norm(s, U, P, wJ, (mode, T_end)),
+           "roofline": roofline(dom, N, K, kernels[dom]["avg_ms"], form, path, traffic),
+           "kernels": kernels}
+    Fs, Bs = stage_work(N)
+    t_stage = wall / stages
+    res["stage"] = {"flop_per_stage": Fs * K, "bytes_per_stage": Bs * K,
+                    "tflops": Fs * K / t_stage / 1e12, "gbs": Bs * K / t_stage / 1e9,
+                    "frac_fp64_roof": (Fs * K / t_stage) / (PEAK_FP64_TFLOPS * 1e12),
+                    "frac_hbm_roof": (Bs * K / t_stage) / (PEAK_HBM_GBS * 1e9)}
+    if keep_state:
+        return res, s, U, P, wJ
+    s.close()
+    del U, R, P, wJ
+    torch.cuda.empty_cache()
+    return res
+
+
+def compare_forms(dg, xyz, e2v, k1d, N, mode, steps, warmup, stream):
+    """FP64 and both precision forms on one mesh and mode: each form's result
+    with its speed-up over FP64, its L2 distance to the FP64 state and whether
+    it is at equal error (within 10 % of the FP64 error)."""
+    import torch
+    base, s64, U64, P, wJ = run_form(dg, xyz, e2v, k1d, N, "fp64", mode, steps, warmup, stream,
+                                     keep_state=True)
+    forms = {}
+    for form in ("fp32_mfma", "split_bf16"):
+        res, sf, Uf, _, _ = run_form(dg, xyz, e2v, k1d, N, form, mode, steps, warmup, stream,
+                                     keep_state=True)
+        res["speedup_vs_fp64"] = res["value"] / base["value"]
+        res["l2_diff_vs_fp64"] = l2_norm(sf, Uf - U64, P, wJ)
+        e64 = base["l2_error_vs_mode"]
+        res["equal_error"] = abs(res["l2_error_vs_mode"] - e64) <= 0.1 * e64
+        sf.close()
+        del Uf
+        torch.cuda.empty_cache()
+        forms[form] = res
+    s64.close()
+    del U64, P, wJ
+    torch.cuda.empty_cache()
+    return base, forms
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--k1d", type=int, default=40)
-    ap.add_argument("--N", type=int, default=4)
+    ap.add_argument("--k1d", type=int, default=64)
+    ap.add_argument("--N", type=int, default=5)
+    ap.add_argument("--extra-N", default="6,7",
+                    help="further orders run after the headline one (comma list, '' for none)")
+    ap.add_argument("--mode", type=int, default=0,
+                    help="wall eigenmode number m of the initial data (0: the equal-error mode "
+                         "of each N)")
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--single", action="store_true",
+                    help="time one path (--precision and the kernel flags) only")
     ap.add_argument("--reference-kernels", action="store_true",
                     help="plain FP64 vector-ALU kernels instead of the matrix-core ones")
     ap.add_argument("--unfused", action="store_true",
@@ -474,10 +710,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 256 MiB buffer 3 times (a plain copy "
                          "of known size for scaling HBM counters)")
-    ap.add_argument("--mode", type=int, default=1, help="wall eigenmode number m of the initial data")
-    ap.add_argument("--no-forms", action="store_true",
-                    help="skip the FP32-MFMA / split-BF16 comparison on the same workload")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-per-worker", type=int, default=4096,
+                    help="elements per CPU worker in the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", action="store_true",
                     help="batched independent problems instead of the bench line")
@@ -491,6 +725,8 @@ def main():
     ap.add_argument("--adjoint-receivers", type=int, default=64)
     ap.add_argument("--adjoint-alpha", type=float, default=1.0,
                     help="flux parameter of the adjoint run (1: the flux of Section 4.3)")
+    ap.add_argument("--adjoint-fd-directions", type=int, default=10,
+                    help="central-difference checks of the adjoint gradient (0: none)")
     ap.add_argument("--advection", action="store_true",
                     help="advection workload (Section 4.1) instead of the bench line")
     ap.add_argument("--advection-k1d", type=int, default=64)
@@ -508,10 +744,24 @@ def main():
               "single-device and is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
+    from synth import hex_pyramid_mesh
+    headline = not (args.study or args.batch or args.adjoint or args.advection)
+    N = args.N
+    xyz = e2v = None
+    cpu = cpu1 = None
+    if headline:
+        xyz, e2v = hex_pyramid_mesh(args.k1d, seed=3 if args.k1d == 64 else 2)
+        if not args.no_cpu_baseline:
+            # the oracle on the host cores, before this process touches the GPU
+            cores = _host_cores()
+            print(f"[bench] CPU baseline: oracle on {cores} cores, then 1", file=sys.stderr,
+                  flush=True)
+            cpu = cpu_baseline(xyz, e2v, N, args.cpu_per_worker, cores)
+            cpu1 = cpu_baseline(xyz, e2v, N, args.cpu_per_worker, 1)
+
     import torch
 
     import paper_1502_07703_amd as dg
-    from synth import hex_pyramid_mesh
 
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -528,120 +778,59 @@ def main():
     if args.advection:
         advection_bench(args)
         return
-    N = args.N
-    Np = n_basis(N)
-    xyz, e2v = hex_pyramid_mesh(args.k1d, seed=2)
     K = e2v.shape[0]
-    solver = dg.Solver(xyz, e2v, N, precision=args.precision,
-                       reference_kernels=args.reference_kernels, unfused=args.unfused,
-                       sum_factorized=args.sum_factorized, groups_per_wave=args.groups,
-                       lds_operators=None if args.lds_operators < 0 else bool(args.lds_operators),
-                       trace_groups=args.trace_groups)
-    # initial data: the unit-cube wall eigenmode (mode m), L2-projected on the device
-    P, wJ = solver.volume_points()
-    U0 = solver.project(wall_mode_values(P, args.mode, 0.0))
-    U = U0.clone()
-    R = solver.empty_state().zero_()
-    dt = solver.stable_dt(0.5)
+    Np = n_basis(N)
     stream = torch.cuda.current_stream()
-
-    solver.step(U, R, dt, args.warmup)
-    torch.cuda.synchronize()
-
-    # Timed region: K steps, each kernel launch bracketed by HIP events on the
-    # launch stream; wall time bracketed by synchronisation.
-    wall, names, ms, cnt = timed_steps(dg, solver, U, R, args.warmup * dt, dt, args.steps, stream)
-    if not torch.isfinite(U).all():
-        print("non-finite state after the timed steps", file=sys.stderr)
-        sys.exit(1)
-
-    stages = 5 * args.steps
-    value = 4 * Np * K * stages / wall / 1e9
-    kernels = {}
-    for i, nm in enumerate(names):
-        avg = ms[i] / max(cnt[i], 1)
-        F, Bb = kernel_work(nm, N)
-        kernels[nm] = {"avg_ms": avg, "launches": int(cnt[i]),
-                       "tflops": F * K / (avg * 1e-3) / 1e12,
-                       "gbs": Bb * K / (avg * 1e-3) / 1e9}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
-    path_key = ("reference" if args.reference_kernels else "sumfact" if args.sum_factorized
-                else "unfused" if args.unfused else "fused")
-    groups = solver.info_groups()
-    traffic = recorded_traffic(dom, f"k1d={args.k1d} N={N} {args.precision} {path_key} g{groups}")
-    Fd, Bd = kernel_work(dom, N)
-    t_d = kernels[dom]["avg_ms"] * 1e-3
-    compute_bound = Fd / (PEAK_FP64_TFLOPS * 1e12) >= Bd / (PEAK_HBM_GBS * 1e9)
-    if compute_bound:
-        ach = Fd * K / t_d / 1e12
-        matrix = not (args.reference_kernels or args.sum_factorized)
-        peak = {"fp64": PEAK_FP64_TFLOPS, "fp32_mfma": PEAK_FP32_TFLOPS,
-                "split_bf16": PEAK_BF16_TFLOPS}[args.precision]
-        roof = {"bound": "mfma" if matrix else "alu", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic, "kernel": dom,
-                "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
+    mode = args.mode or EQUAL_ERROR_MODE.get(N, 1)
+    path = ("reference" if args.reference_kernels else "sumfact" if args.sum_factorized
+            else "unfused" if args.unfused else "fused")
+    workload = (f"unit cube, {args.k1d}^3 perturbed hexes x 6 = {K} pyramids, N={N}, 4 fields, "
+                f"walls, penalty flux, LSRK(5,4), projected wall eigenmode m={mode}")
+    if args.single or path != "fused" or args.precision != "fp64":
+        main_res = run_form(dg, xyz, e2v, args.k1d, N, args.precision, mode, args.steps,
+                            args.warmup, stream, path=path, groups=args.groups,
+                            trace_groups=args.trace_groups,
+                            lds_operators=None if args.lds_operators < 0 else bool(args.lds_operators))
+        forms, orders = None, {}
     else:
-        ach = Bd * K / t_d / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "kernel": dom,
-                "per_launch": {"flop": Fd * K, "bytes": Bd * K}}
-    Fs, Bs = stage_work(N)
-    t_stage = wall / stages
-    whole = {"flop_per_stage": Fs * K, "bytes_per_stage": Bs * K,
-             "tflops": Fs * K / t_stage / 1e12, "gbs": Bs * K / t_stage / 1e9,
-             "frac_fp64_roof": (Fs * K / t_stage) / (PEAK_FP64_TFLOPS * 1e12),
-             "frac_hbm_roof": (Bs * K / t_stage) / (PEAK_HBM_GBS * 1e9)}
+        main_res, forms = compare_forms(dg, xyz, e2v, args.k1d, N, mode, args.steps, args.warmup,
+                                        stream)
+        orders = {}
+        for n2 in [int(x) for x in args.extra_N.split(",") if x.strip()]:
+            m2 = EQUAL_ERROR_MODE.get(n2, 1)
+            b2, f2 = compare_forms(dg, xyz, e2v, args.k1d, n2, m2, args.steps, args.warmup,
+                                   stream)
+            orders[str(n2)] = {"mode": m2, "fp64": b2, **f2}
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_res["value"],
         "unit": "GDOF·stages/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32_mfma": "f32 contractions, f64 state",
-                  "split_bf16": "bf16x3 contractions, f64 state"}[args.precision],
+        "dtype": FORM_DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"unit cube, {args.k1d}^3 perturbed hexes x 6 = {K} pyramids, "
-                               f"N={N}, 4 fields, walls, penalty flux, LSRK(5,4)",
-                   "k1d": args.k1d, "nelems": K, "N": N, "Np": Np, "dof": 4 * Np * K,
-                   "precision": args.precision, "stages_per_step": 5, "dt": dt,
-                   "groups_per_wave": groups,
-                   "kernels": ("reference (vector ALU)" if args.reference_kernels else
-                               "sum-factorised, fused" if args.sum_factorized else
-                               "matrix core, unfused" if args.unfused else "matrix core, fused")},
-        "roofline": roof,
-        "stage": whole,
-        "kernels": kernels,
+        "config": {"workload": workload, "k1d": args.k1d, "nelems": K, "N": N, "Np": Np,
+                   "dof": 4 * Np * K, "precision": args.precision, "stages_per_step": 5,
+                   "dt": main_res["dt"], "mode": mode,
+                   "groups_per_wave": main_res["groups_per_wave"],
+                   "kernels": {"reference": "reference (vector ALU)",
+                               "sumfact": "sum-factorised, fused", "unfused":
+                               "matrix core, unfused", "fused": "matrix core, fused"}[path]},
+        "roofline": main_res["roofline"],
+        "stage": main_res["stage"],
+        "kernels": main_res["kernels"],
+        "l2_error_vs_mode": {"mode": mode, "t": main_res["t_end"],
+                             "value": main_res["l2_error_vs_mode"]},
     }
-    # Error of the run against the exact mode at the final time, and the
-    # precision forms on the same workload, initial data and step count.
-    T_end = (args.warmup + args.steps) * dt
-    e_main = l2_norm(solver, U, P, wJ, (args.mode, T_end))
-    out["l2_error_vs_mode"] = {"mode": args.mode, "t": T_end, "value": e_main}
-    if (not args.no_forms and args.precision == "fp64" and not args.reference_kernels
-            and not args.sum_factorized and not args.unfused):
-        forms = {}
-        for form in ("fp32_mfma", "split_bf16"):
-            with dg.Solver(xyz, e2v, N, precision=form) as sf:
-                Uf = U0.clone()
-                Rf = sf.empty_state().zero_()
-                sf.step(Uf, Rf, dt, args.warmup)
-                wf, nf, msf, cf = timed_steps(dg, sf, Uf, Rf, args.warmup * dt, dt, args.steps,
-                                              stream)
-                e_f = l2_norm(sf, Uf, P, wJ, (args.mode, T_end))
-                d_f = l2_norm(sf, Uf - U, P, wJ)
-                vf = 4 * Np * K * stages / wf / 1e9
-                forms[form] = {
-                    "value": vf, "speedup_vs_fp64": vf / value,
-                    "l2_error_vs_mode": e_f, "l2_diff_vs_fp64": d_f,
-                    "equal_error": abs(e_f - e_main) <= 0.1 * e_main,
-                    "kernels": {nm: {"avg_ms": msf[i] / max(cf[i], 1)} for i, nm in enumerate(nf)}}
+    if forms is not None:
         out["precision_forms"] = forms
+        out["orders"] = orders
     if args.copy_calibration:
         nbytes = 256 << 20
         a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -650,10 +839,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 3}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(xyz, e2v, N, solver.unpack(U0).cpu().numpy(),
-                                           args.cpu_sample)
-    solver.close()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["cpu_baseline_1core"] = cpu1
     print(json.dumps(out), flush=True)
 
 

@@ -4,6 +4,7 @@ import subprocess
 import sys
 
 import bench
+import numpy as np
 
 
 def test_more_than_one_gpu_is_refused():
@@ -44,3 +45,21 @@ def test_plane_wave_dot_matches_matmul():
     P = np.random.default_rng(0).standard_normal((7, 5, 3))
     k = np.array([1.5, -0.2, 0.7])
     assert np.allclose(bench._dot3(P, k), P @ k, rtol=1e-15, atol=1e-15)
+
+
+def test_cpu_baseline_closure_holds_every_face_neighbour():
+    """The CPU baseline evaluates the oracle on a sub-mesh made of its sample
+    and their neighbours: every face neighbour of a sampled element must be in
+    it, so the sampled right-hand sides equal those on the whole mesh."""
+    import bench
+    from oracle import AcousticDG
+    from synth import hex_pyramid_mesh, random_state
+    xyz, e2v = hex_pyramid_mesh(4, seed=3)
+    K = e2v.shape[0]
+    S = np.sort(np.random.default_rng(1).choice(K, 40, replace=False))
+    xs, es, loc, sub = bench._face_closure(xyz, e2v, S)
+    assert np.array_equal(sub[loc], S)
+    U = random_state(K, 2, seed=4)
+    full = AcousticDG(xyz, e2v, 2, elems=S).rhs(U)
+    part = AcousticDG(xs, es, 2, elems=loc).rhs(U[sub])
+    assert np.abs(full - part).max() <= 1e-14 * np.abs(full).max()
