@@ -89,10 +89,15 @@ typedef struct {
                                            launches instead of one fused stage kernel */
 #define DGPYR_FLAG_SUM_FACTORIZED 4u    /* FP64 sum-factorised evaluation of the same
                                            contractions through the collapsed tensor
-                                           structure of the basis (Section 4.4), fused;
-                                           setup returns E_UNSUPPORTED unless the
-                                           library was built with
-                                           DGPYR_ENABLE_SUM_FACTORIZED          */
+                                           structure of the basis (the cheaper volume
+                                           integrals of Section 4.4): O(N^4) instead
+                                           of O(N^6) flops per element; on meshes of
+                                           hexahedra split into 6 pyramids (groups of
+                                           6 consecutive elements around one apex)
+                                           the triangle-face traces stay on chip.
+                                           FP64 precision form only (else
+                                           E_UNSUPPORTED); E_UNSUPPORTED too if a
+                                           kernel's resources exceed the device's */
 #define DGPYR_FLAG_ADJOINT 8u           /* reserve at setup every device buffer the
                                            discrete-adjoint calls use (ten state-sized
                                            arrays, one trace-sized array) and receiver

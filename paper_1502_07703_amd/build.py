@@ -24,7 +24,7 @@ SOURCES = [
     "kernels_fp64.hip",
     "kernels_mfma.hip",
     "kernels_aux.hip",
-    "kernels_sf.hip",
+    "kernels_sumfact.hip",
     "kernels_bf16.hip",
     "batch.hip",
     "kernels_adjoint.hip",

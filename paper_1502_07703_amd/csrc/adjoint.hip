@@ -166,6 +166,10 @@ dgpyr_status dgpyr_adjoint_step(dgpyr_ctx* c, const double* U0, double* Ubar, do
     c->mesh.dt_time = 0.0;
     if (e == hipSuccess) e = run_stage(c, 0, W + st * n, F, nullptr, 0.0, 0.0, 0.0, s, nullptr);
     if (e == hipSuccess) e = dgpyr::launch_kappa_grad(*c, grad, Rb, F, dt, s);
+    // the sum-factorised stage keeps (p, u.n) traces: the penalty-coefficient
+    // gradient needs all four fields' traces of the stage input
+    if (e == hipSuccess && c->sum_factorized)
+      e = dgpyr::launch_trace_mfma(*c, W + st * n, c->T, s);
     // A^T Rb
     // (c->T now holds the traces of the stage input W_s)
     if (e == hipSuccess) e = dgpyr::launch_adjoint_scale(*c, Rb, c->adj_mu, s);

@@ -202,12 +202,13 @@ hipError_t run_stage(dgpyr_ctx* c, int mode, const double* U, double* out, doubl
     return e;
   }
   if (c->sum_factorized) {
+    // traces as (p, u.n) pairs: base faces only on whole hexahedra
     if (tm) tm->begin(0);
-    hipError_t e = dgpyr::launch_trace_sf(*c, U, c->T, s);
+    hipError_t e = dgpyr::launch_sf_trace(*c, U, c->T, s);
     if (tm) tm->end();
     if (e != hipSuccess) return e;
     if (tm) tm->begin(1);
-    e = dgpyr::launch_stage_sf(*c, mode, U, c->T, out, R, ra, rb, dt, s);
+    e = dgpyr::launch_sf_stage(*c, mode, U, c->T, out, R, ra, rb, dt, s);
     if (tm) tm->end();
     return e;
   }
@@ -542,13 +543,6 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   if ((opts->flags & DGPYR_FLAG_SUM_FACTORIZED) &&
       (opts->precision != DGPYR_FP64 || (opts->flags & (DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED))))
     return fail(DGPYR_E_UNSUPPORTED, "the sum-factorised kernels are FP64 and fused only");
-#ifndef DGPYR_ENABLE_SUM_FACTORIZED
-  // The sum-factorised kernels are held back from device runs until a device
-  // fault seen in a run that included them is explained; they are built and
-  // checked only in the CPU emulation build, which defines this macro.
-  if (opts->flags & DGPYR_FLAG_SUM_FACTORIZED)
-    return fail(DGPYR_E_UNSUPPORTED, "the sum-factorised kernels are disabled in this build");
-#endif
   if (!(opts->alpha >= 0.0)) return fail(DGPYR_E_ARG, "alpha must be >= 0");
   if (opts->precision != DGPYR_FP64 && opts->precision != DGPYR_FP32_MFMA &&
       opts->precision != DGPYR_SPLIT_BF16)
@@ -604,6 +598,9 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   c->reference_kernels = (opts->flags & DGPYR_FLAG_REFERENCE_KERNELS) != 0;
   c->unfused = (opts->flags & DGPYR_FLAG_UNFUSED) != 0;
   c->sum_factorized = (opts->flags & DGPYR_FLAG_SUM_FACTORIZED) != 0;
+  // whole hexahedra per workgroup when the mesh comes in groups of 6 pyramids
+  // around a common apex and such a group fits the workgroup's LDS at this N
+  c->sf_local = c->sum_factorized && c->hex_groups && dgpyr::sf_local_possible(*c);
   c->mfma_groups = default_groups(N, opts->precision);
   // Operator staging in LDS: measured at 384000 pyramids, N = 4, it speeds the
   // FP32 stage up (2.47 -> 2.29 ms) but slows the FP64 one (3.09 -> 3.44 ms;
@@ -615,6 +612,11 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   dgpyr_status st = ed == hipSuccess ? scratch_for_current_device(c->device)
                                      : hip_fail(ed, "hipGetDevice");
   if (st == DGPYR_OK) st = upload_context(c, ops, md);
+  if (st == DGPYR_OK && c->sum_factorized) {
+    std::string rmsg;  // LDS, private memory and block size against the device
+    st = dgpyr::sf_check_resources(*c, rmsg);
+    if (st != DGPYR_OK) st = fail(st, rmsg);
+  }
   if (st == DGPYR_OK && (opts->flags & DGPYR_FLAG_ADJOINT)) st = reserve_adjoint(c);
   if (st != DGPYR_OK) {
     free_ctx(c);

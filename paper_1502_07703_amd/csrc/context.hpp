@@ -154,6 +154,8 @@ struct dgpyr_ctx {
   bool reference_kernels = false;  // plain FP64 VALU kernels instead of MFMA
   bool unfused = false;            // separate matrix-core volume and surface launches
   bool sum_factorized = false;     // FP64 sum-factorised kernels
+  bool sf_local = false;           // sum-factorised stage on whole hexahedra (triangle
+                                   // traces exchanged in LDS, base traces in T)
   int mfma_groups = 1;             // 4-element groups per wave (fused matrix core)
   bool lds_operators = false;      // stage operator tiles in LDS per workgroup
   int trace_groups = 0;            // 4-element groups per wave of the trace (0: by N)
@@ -206,10 +208,16 @@ hipError_t launch_eval(const dgpyr_ctx& c, const double* U, double* f, hipStream
 // Matrix-core kernels (kernels_mfma.hip).
 hipError_t launch_volume_mfma(const dgpyr_ctx& c, const double* U, double* vol, hipStream_t s);
 hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
-// Sum-factorised FP64 kernels (kernels_sf.hip).
-hipError_t launch_trace_sf(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
-hipError_t launch_stage_sf(const dgpyr_ctx& c, int mode, const double* U, const double* T,
+// Sum-factorised FP64 kernels (kernels_sumfact.hip).  Traces are (p, u.n) pairs,
+// T2 [K][NF][(N+1)^2][2] with NF = 1 (base faces, sf_local) or 5.
+hipError_t launch_sf_trace(const dgpyr_ctx& c, const double* U, double* T2, hipStream_t s);
+hipError_t launch_sf_stage(const dgpyr_ctx& c, int mode, const double* U, const double* T2,
                            double* out, double* R, double ra, double rb, double dt, hipStream_t s);
+// Whether whole hexahedra fit one workgroup at the context's N.
+bool sf_local_possible(const dgpyr_ctx& c);
+// LDS, private memory and block size of the sum-factorised kernels against the
+// device's limits; E_UNSUPPORTED with a message when a kernel does not fit.
+dgpyr_status sf_check_resources(const dgpyr_ctx& c, std::string& msg);
 // Split-BF16 fused stage (kernels_bf16.hip).
 hipError_t launch_stage_bf16(const dgpyr_ctx& c, int mode, const double* U, const double* T,
                              double* out, double* R, double ra, double rb, double dt,

@@ -1,0 +1,739 @@
+// Sum-factorised FP64 stage: the volume term, surface term, inverse mass and
+// LSRK update evaluated through the collapsed tensor structure of the
+// semi-nodal basis (the cheaper evaluation of volume integrals proposed in
+// Section 4.4),
+//   phi_ijk(a, b, c) = l^k_i(a) l^k_j(b) g_k(c),  g_k = h^k P^{(2k+3,0)}_{N-k}(c),
+// h = (1-c)/2, on the tensor cubature (a_p, b_m, c_r) of Section 4.1.  Every
+// contraction is a product with a one-dimensional factor, so a stage costs
+// O(N^4) per element instead of the O(N^6) of the dense operators; results
+// equal the dense contractions up to rounding order.
+//
+// Derivatives in the reference coordinates (r, s, t) of one field u:
+//   d_r u = sum_k Gt_k(c) sum_j l_j(b) sum_i l'_i(a) u_ijk,
+//   d_s u = sum_k Gt_k(c) sum_j l'_j(b) sum_i l_i(a) u_ijk,
+//   d_t u = sum_k g'_k(c) sum_j l_j(b) sum_i l_i(a) u_ijk
+//           + (1+a)/2 d_r u + (1+b)/2 d_s u,
+// with Gt_k = h^(k-1) P_{N-k} (the factor 2/(1-c) of the collapsed
+// derivatives absorbed).  The metric J dR/dx depends on (a, b) only (Lemma 1
+// generalised), so it is evaluated once per (a, b) column.
+//
+// Faces.  A trace is kept as two numbers per face point, the pressure and the
+// normal velocity u . n with the element's own outward unit normal n: the
+// penalty flux (Section 4.3) needs only the jumps [[p]] and n . [[u]], and on a
+// conforming face the neighbour's outward normal is -n.  The pyramids of one
+// hexahedron pair their four triangle faces among themselves; when the mesh
+// comes in such groups a workgroup owns whole hexahedra and exchanges the
+// triangle traces in LDS, and only the quadrilateral base traces go through
+// HBM (written by k_sf_trace).  Otherwise k_sf_trace writes the traces of all
+// five faces and the stage reads its neighbours' from HBM.
+//
+// Work shape.  A workgroup owns E elements and one thread per (element, a, b)
+// column.  The four fields are processed one at a time through LDS: the
+// a-direction contraction (all threads), then per column the b- and c-
+// direction contractions, the FP64 metric and the projection onto the c
+// factors, accumulated in registers across the fields; after the face fluxes
+// the projection is finished field by field (b-direction, then a-direction
+// with the triangle lifts, inverse mass and the LSRK stage).  LDS stays under
+// 60 KiB per workgroup and no kernel keeps arrays in private memory; setup
+// checks both (hipFuncGetAttributes against the device's limits) before the
+// first launch.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "context.hpp"
+#include "flux.hpp"
+#include "geom.hpp"
+
+namespace dgpyr {
+namespace {
+
+constexpr int kLdsBudget = 60 * 1024;  // bytes of LDS a workgroup may use
+// Private memory a work item may reserve: the compiler keeps a small frame of
+// up to 68 bytes per lane for some of these kernels that no instruction
+// touches (the register scavenger's reserve); anything larger would mean
+// arrays spilled to private memory.
+constexpr size_t kPrivateBudget = 256;
+
+__device__ __host__ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
+
+// Sizes of the sum-factorised stage at degree N.
+template <int N>
+struct SfDims {
+  static constexpr int n1 = N + 1;
+  static constexpr int n2 = n1 * n1;
+  static constexpr int n3 = n2 * n1;
+  static constexpr int Np = n1 * (n1 + 1) * (2 * n1 + 1) / 6;
+  static constexpr int KJ = n1 * (n1 + 1) / 2;  // pairs (k, j <= k)
+  static constexpr int Nfc = 5 * n2;
+  // per-element LDS regions (doubles):
+  static constexpr int UD = KJ * n1;      // U of one field, then D [kj][p]
+  static constexpr int AB = 2 * KJ * n1;  // A, A' [2][kj][p], then B [k][m][p] (n3 <= AB)
+  static constexpr int TT = 8 * n2;       // triangle traces [face][p, u.n][point]
+  // folded triangle fluxes [face][2][k][p] overwrite the traces when every
+  // thread owns at most one (element, face, a) item (4 n1 <= n2), else they
+  // need a region of their own
+  static constexpr bool kSeparateC = 4 * n1 > n2;
+  static constexpr int CC = kSeparateC ? 8 * n2 : 0;
+  static constexpr int kTables = 16 + 16 + 5 + 10;  // vertices, normals, rho c, ints
+  static constexpr int PER_ELEM = kTables + UD + AB + TT + CC;
+  static constexpr int PERM_BYTES = 10 * n2 * 4;
+  static constexpr int bytes(int E) { return E * PER_ELEM * 8 + PERM_BYTES; }
+  // elements per workgroup when hexahedra (6 elements) are kept whole, 0 if
+  // not even one fits; at most 512 columns
+  static constexpr int hex_elems() {
+    int best = 0;
+    for (int H = 1; 6 * H * n2 <= 512 && bytes(6 * H) <= kLdsBudget; ++H) best = 6 * H;
+    return best;
+  }
+  static constexpr int free_elems() {
+    int best = 1;
+    for (int E = 1; E * n2 <= 512 && bytes(E) <= kLdsBudget; ++E) best = E;
+    return best;
+  }
+};
+
+template <int N, bool LOCAL>
+struct SfShape {
+  using D = SfDims<N>;
+  static constexpr int E = LOCAL ? D::hex_elems() : D::free_elems();
+  static constexpr int THREADS = round64(E * D::n2);
+};
+
+__device__ __forceinline__ int kofs(int k) { return k * (k + 1) * (2 * k + 1) / 6; }
+__device__ __forceinline__ int kjofs(int k) { return k * (k + 1) / 2; }
+
+// (k, j) of a pair index kj = k (k+1)/2 + j.
+__device__ __forceinline__ void kj_split(int kj, int& k, int& j) {
+  k = 0;
+  while (kjofs(k + 1) <= kj) ++k;
+  j = kj - kjofs(k);
+}
+
+// Penalty flux from the jumps at one face point (Section 4.3):
+//   Fp = w (n.[[u]] - tau_p [[p]]) / 2,  Pu = w ([[p]] - tau_u n.[[u]]) / 2,
+// the velocity rows' flux being n Pu; w = face weight x surface Jacobian.
+__device__ __forceinline__ void jump_flux(double jp, double jun, double zm, double zp,
+                                          double alpha, double w, double& Fp, double& Pu) {
+  const double zavg = 0.5 * (zm + zp);
+  const double taup = alpha / zavg, tauu = alpha * zavg;
+  Fp = 0.5 * w * (jun - taup * jp);
+  Pu = 0.5 * w * (jp - tauu * jun);
+}
+
+// Exterior values (p+, n.u+) at a face point from the neighbour's stored
+// (p, u.n') with n' = -n, or the mirror state of the boundary condition.
+__device__ __forceinline__ void exterior(bool inner, double nbp, double nbun, double pm, double unm,
+                                         int bc, double& pp, double& unp) {
+  if (inner) {
+    pp = nbp;
+    unp = -nbun;
+  } else if (bc == DGPYR_BC_WALL) {  // p+ = p-, u+ = u- - 2 (n.u-) n
+    pp = pm;
+    unp = -unm;
+  } else {  // free surface: p+ = -p-, u+ = u-
+    pp = -pm;
+    unp = unm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Traces: (p, u.n) at the base points (NF = 1) or at the points of all five
+// faces (NF = 5) of every element, T2[K][NF][n2][2].  One thread per
+// (element, face, a-index p) evaluates the n1 points of its line through the
+// a-direction contraction shared by them.
+template <int N, int NF>
+struct TraceShape {
+  using D = SfDims<N>;
+  static constexpr int per_elem = 4 * D::Np + 2 * NF * D::n2;  // doubles
+  static constexpr int E = (40 * 1024) / (per_elem * 8) < 1 ? 1
+                           : (40 * 1024) / (per_elem * 8) > 32 ? 32
+                                                                : (40 * 1024) / (per_elem * 8);
+  static constexpr int THREADS = round64(E * NF * D::n1);
+};
+
+template <int N, int NF>
+__global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
+    const double* __restrict__ U, double* __restrict__ T2, SfOps sf, DevOps ops,
+    const double* __restrict__ verts, int64_t K) {
+  using D = SfDims<N>;
+  using TS = TraceShape<N, NF>;
+  constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, E = TS::E, NT = TS::THREADS;
+  __shared__ double sU[E][4 * Np];
+  __shared__ double sO[E][NF * n2 * 2];
+  __shared__ double sX[E][16];
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)(K - e0 < E ? K - e0 : E);
+  for (int x = tid; x < ne * 4 * Np; x += NT) sU[x / (4 * Np)][x % (4 * Np)] = U[e0 * 4 * Np + x];
+  for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
+  __syncthreads();
+  for (int x = tid; x < ne * NF * n1; x += NT) {
+    const int le = x / (NF * n1), rem = x % (NF * n1);
+    const int f = rem / n1, p = rem % n1;
+    const double* xv = sX[le];
+    double outp[n1], outu[n1];
+#pragma unroll
+    for (int m = 0; m < n1; ++m) outp[m] = outu[m] = 0.0;
+    double tn[3] = {0.0, 0.0, 0.0};
+    if (f > 0) {  // planar triangle: one unit normal
+      double nr[4];
+      face_normal_unit(xv, f, ops.fa[f * n2], ops.fb[f * n2], nr);
+      tn[0] = nr[0];
+      tn[1] = nr[1];
+      tn[2] = nr[2];
+    }
+#pragma unroll
+    for (int fld = 0; fld < 4; ++fld) {
+      const double* u = sU[le] + fld * Np;
+      double val[n1];
+#pragma unroll
+      for (int m = 0; m < n1; ++m) val[m] = 0.0;
+#pragma unroll
+      for (int k = 0; k <= N; ++k) {
+        const double* uk = u + kofs(k);
+        if (f == 0) {
+          // base (c = -1): g_k(-1) sum_j l_j(b_m) sum_i l_i(a_p) u_ijk
+          const double* La_p = sf.La + (k * n1 + p) * n1;
+          double A[n1];
+#pragma unroll
+          for (int j = 0; j <= k; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i <= k; ++i) acc += La_p[i] * uk[j * (k + 1) + i];
+            A[j] = sf.Gb[k] * acc;
+          }
+#pragma unroll
+          for (int m = 0; m < n1; ++m) {
+            const double* La_m = sf.La + (k * n1 + m) * n1;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j <= k; ++j) acc += La_m[j] * A[j];
+            val[m] += acc;
+          }
+        } else {
+          // a = -1 / +1 (f = 1 / 2): sum_j l_j(sigma_p) sum_i l_i(-+1) u_ijk;
+          // b = -1 / +1 (f = 3 / 4): sum_j l_j(-+1) sum_i l_i(sigma_p) u_ijk;
+          // then g_k at the Gauss-Jacobi(1,0) nodes c_m
+          const double* La_p = sf.La + (k * n1 + p) * n1;
+          const double* Le_s = sf.Le + (k * 2 + ((f == 2 || f == 4) ? 1 : 0)) * n1;
+          double Y = 0.0;
+#pragma unroll
+          for (int j = 0; j <= k; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i <= k; ++i) acc += (f <= 2 ? Le_s[i] : La_p[i]) * uk[j * (k + 1) + i];
+            Y += (f <= 2 ? La_p[j] : Le_s[j]) * acc;
+          }
+#pragma unroll
+          for (int m = 0; m < n1; ++m) val[m] += sf.Gf[m * n1 + k] * Y;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < n1; ++m) {
+        if (fld == 0) {
+          outp[m] = val[m];
+        } else {
+          double nd = tn[fld - 1];
+          if (f == 0) {  // the base normal varies with (a, b)
+            double nr[4];
+            face_normal_unit(xv, 0, ops.xg[p], ops.xg[m], nr);
+            nd = nr[fld - 1];
+          }
+          outu[m] += nd * val[m];
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < n1; ++m) {
+      const int pt = f * n2 + p + n1 * m;
+      sO[le][2 * pt + 0] = outp[m];
+      sO[le][2 * pt + 1] = outu[m];
+    }
+  }
+  __syncthreads();
+  // coalesced store: the block's rows are contiguous in T2
+  for (int x = tid; x < ne * NF * n2 * 2; x += NT)
+    T2[e0 * NF * n2 * 2 + x] = sO[x / (NF * n2 * 2)][x % (NF * n2 * 2)];
+}
+
+// ---------------------------------------------------------------------------
+// Fused stage.  LOCAL: workgroups own whole hexahedra (triangle neighbours
+// are in the workgroup, T2 holds base traces only); otherwise T2 holds the
+// traces of all five faces and triangle neighbours outside the workgroup are
+// read from it.
+template <int N, int MODE, bool LOCAL>
+__global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
+    const double* U, const double* __restrict__ T2, SfOps sf, DevOps ops, DevMesh mesh,
+    double* out, double* R, double ra, double rb, double dt) {
+  using D = SfDims<N>;
+  constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, KJ = D::KJ;
+  constexpr int E = SfShape<N, LOCAL>::E, NT = SfShape<N, LOCAL>::THREADS;
+  constexpr int NF = LOCAL ? 1 : 5;  // faces per element row of T2
+  constexpr int CREG = D::kSeparateC ? D::CC : D::TT;
+  __shared__ double sX[E][16];
+  __shared__ double sN[E][4][4];   // triangle faces 1..4: unit normal, sJ
+  __shared__ double sZ[E][5];      // rho c across each face (own on the boundary)
+  __shared__ int sNb[E][5][4];     // neighbour, its index in the workgroup or -1, its face, permutation row
+  __shared__ double sUD[E][D::UD];
+  __shared__ double sAB[E][D::AB];
+  __shared__ double sTT[E][D::TT];
+  __shared__ double sCC[D::kSeparateC ? E : 1][D::kSeparateC ? D::CC : 1];
+  __shared__ int sPerm[10 * n2];
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)(mesh.K - e0 < E ? mesh.K - e0 : E);
+
+  // ---- tables: vertices, face neighbours, triangle normals, permutations
+  for (int x = tid; x < E * 16; x += NT) {
+    const int le = x / 16;
+    sX[le][x % 16] = le < ne ? mesh.verts[(e0 + le) * 16 + x % 16] : 0.0;
+  }
+  for (int x = tid; x < 10 * n2; x += NT) sPerm[x] = ops.perm[x];
+  __syncthreads();
+  for (int x = tid; x < E * 5; x += NT) {
+    const int le = x / 5, f = x % 5;
+    int nb = -1, loc = -1, nf = 0, prow = 0;
+    double z = 1.0;
+    if (le < ne) {
+      const int64_t e = e0 + le;
+      nb = mesh.conn[e * 8 + f];
+      z = mesh.mat[e * 4 + 2];
+      if (nb >= 0) {
+        const int code = (mesh.conn[e * 8 + 5] >> (6 * f)) & 63;
+        nf = code & 7;
+        prow = (f == 0 ? (code >> 3) : 8 + (code >> 3)) * n2;
+        loc = (nb >= e0 && nb < e0 + ne) ? (int)(nb - e0) : -1;
+        z = mesh.mat[(int64_t)nb * 4 + 2];
+      }
+      if (f > 0) face_normal_unit(sX[le], f, ops.fa[f * n2], ops.fb[f * n2], sN[le][f - 1]);
+    }
+    sNb[le][f][0] = nb;
+    sNb[le][f][1] = loc;
+    sNb[le][f][2] = nf;
+    sNb[le][f][3] = prow;
+    sZ[le][f] = z;
+  }
+
+  // ---- column of this thread: element le, base point (p, m)
+  const bool col = tid < ne * n2;
+  const int le = col ? tid / n2 : 0;
+  const int pm = tid % n2, p = pm % n1, m = pm / n1;
+  const int64_t e = e0 + le;
+  double adj[9], Jc;
+  pyr_metric(sX[le], ops.xg[p], ops.xg[m], adj, &Jc);
+  const double wab = 0.25 * ops.wf[pm];  // w_p w_m / 4
+  const double ha = 0.5 * (1.0 + ops.xg[p]), hb = 0.5 * (1.0 + ops.xg[m]);
+  double bacc[4][n1];  // projection onto g_k(c_r): [field][k]
+  double qp[n1];       // w-less divergence of u at c_r
+  double tb[4];        // own base trace of each field at (p, m)
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    tb[f] = 0.0;
+#pragma unroll
+    for (int k = 0; k < n1; ++k) bacc[f][k] = 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < n1; ++r) qp[r] = 0.0;
+
+  // ---- volume term and own traces, one field at a time
+#pragma unroll
+  for (int fld = 0; fld < 4; ++fld) {
+    for (int x = tid; x < E * Np; x += NT) {
+      const int l = x / Np, n = x % Np;
+      sUD[l][n] = l < ne ? U[((e0 + l) * 4 + fld) * Np + n] : 0.0;
+    }
+    __syncthreads();
+    // a-direction: A[kj][p] = sum_i l_i(a_p) u_ijk, A'[kj][p] with l'_i(a_p)
+    for (int x = tid; x < ne * KJ * n1; x += NT) {
+      const int l = x / (KJ * n1), rem = x % (KJ * n1);
+      const int kj = rem / n1, pp = rem % n1;
+      int k, j;
+      kj_split(kj, k, j);
+      const double* u = sUD[l] + kofs(k) + j * (k + 1);
+      const double* La = sf.La + (k * n1 + pp) * n1;
+      const double* Da = sf.Da + (k * n1 + pp) * n1;
+      double a = 0.0, ad = 0.0;
+      for (int i = 0; i <= k; ++i) {
+        a += La[i] * u[i];
+        ad += Da[i] * u[i];
+      }
+      sAB[l][kj * n1 + pp] = a;
+      sAB[l][KJ * n1 + kj * n1 + pp] = ad;
+    }
+    // triangle traces of this field: item (element, face, edge point)
+    for (int x = tid; x < ne * 4 * n1; x += NT) {
+      const int l = x / (4 * n1), rem = x % (4 * n1);
+      const int ft = rem / n1, pp = rem % n1, f = ft + 1;
+      const double* Le_s = sf.Le + ((f == 2 || f == 4) ? 1 : 0) * n1;
+      double val[n1];
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) val[mm] = 0.0;
+#pragma unroll
+      for (int k = 0; k <= N; ++k) {
+        const double* uk = sUD[l] + kofs(k);
+        const double* La_p = sf.La + (k * n1 + pp) * n1;
+        const double* Le_k = Le_s + k * 2 * n1;
+        double Y = 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i <= k; ++i) acc += (f <= 2 ? Le_k[i] : La_p[i]) * uk[j * (k + 1) + i];
+          Y += (f <= 2 ? La_p[j] : Le_k[j]) * acc;
+        }
+#pragma unroll
+        for (int mm = 0; mm < n1; ++mm) val[mm] += sf.Gf[mm * n1 + k] * Y;
+      }
+      double* tt = sTT[l] + ft * 2 * n2;
+      const double nd = fld == 0 ? 0.0 : sN[l][ft][fld - 1];
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) {
+        const int pt = pp + n1 * mm;
+        if (fld == 0) tt[pt] = val[mm];
+        else if (fld == 1) tt[n2 + pt] = nd * val[mm];
+        else tt[n2 + pt] += nd * val[mm];
+      }
+    }
+    __syncthreads();
+    // b- and c-directions, metric and projection along c, per column
+    if (col) {
+      double s0[n1], sa[n1], sb[n1];
+#pragma unroll
+      for (int k = 0; k < n1; ++k) {
+        const double* La_m = sf.La + (k * n1 + m) * n1;
+        const double* Da_m = sf.Da + (k * n1 + m) * n1;
+        double x0 = 0.0, xa = 0.0, xb = 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) {
+          const double A = sAB[le][(kjofs(k) + j) * n1 + p];
+          const double Ad = sAB[le][KJ * n1 + (kjofs(k) + j) * n1 + p];
+          x0 += La_m[j] * A;
+          xa += La_m[j] * Ad;
+          xb += Da_m[j] * A;
+        }
+        s0[k] = x0;
+        sa[k] = xa;
+        sb[k] = xb;
+        tb[fld] += sf.Gb[k] * x0;
+      }
+#pragma unroll
+      for (int r = 0; r < n1; ++r) {
+        double dr = 0.0, ds = 0.0, dtp = 0.0;
+#pragma unroll
+        for (int k = 0; k < n1; ++k) {
+          dr += sf.Gt[r * n1 + k] * sa[k];
+          ds += sf.Gt[r * n1 + k] * sb[k];
+          dtp += sf.Gp[r * n1 + k] * s0[k];
+        }
+        const double dtt = dtp + ha * dr + hb * ds;
+        if (fld == 0) {
+          // Q_{u_d} = w sum_rho adj[rho][d] d_rho p, projected onto g_k(c_r)
+          const double w = wab * sf.wc[r];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double q = w * (adj[d] * dr + adj[3 + d] * ds + adj[6 + d] * dtt);
+#pragma unroll
+            for (int k = 0; k < n1; ++k) bacc[1 + d][k] += sf.G[r * n1 + k] * q;
+          }
+        } else {
+          const int d = fld - 1;
+          qp[r] += adj[d] * dr + adj[3 + d] * ds + adj[6 + d] * dtt;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- base face: flux at (p, m) from the own traces and the neighbour's
+  if (col) {
+#pragma unroll
+    for (int r = 0; r < n1; ++r) {
+      const double w = wab * sf.wc[r] * qp[r];
+#pragma unroll
+      for (int k = 0; k < n1; ++k) bacc[0][k] += sf.G[r * n1 + k] * w;
+    }
+    double nr[4];
+    face_normal_unit(sX[le], 0, ops.xg[p], ops.xg[m], nr);
+    const double pmv = tb[0];
+    const double unm = nr[0] * tb[1] + nr[1] * tb[2] + nr[2] * tb[3];
+    const int nb = sNb[le][0][0];
+    double nbp = 0.0, nbun = 0.0;
+    if (nb >= 0) {
+      const int q2 = sPerm[sNb[le][0][3] + pm];
+      const double* tp = T2 + (((int64_t)nb * NF + sNb[le][0][2]) * n2 + q2) * 2;
+      nbp = tp[0];
+      nbun = tp[1];
+    }
+    double pp, unp, Fp, Pu;
+    exterior(nb >= 0, nbp, nbun, pmv, unm, mesh.bc, pp, unp);
+    jump_flux(pp - pmv, unp - unm, mesh.mat[e * 4 + 2], sZ[le][0], mesh.alpha,
+              ops.wf[pm] * nr[3], Fp, Pu);
+#pragma unroll
+    for (int k = 0; k < n1; ++k) {
+      const double g = sf.Gb[k];
+      bacc[0][k] += g * Fp;
+      bacc[1][k] += g * nr[0] * Pu;
+      bacc[2][k] += g * nr[1] * Pu;
+      bacc[3][k] += g * nr[2] * Pu;
+    }
+  }
+
+  // ---- triangle faces: fluxes along each edge-point line, folded onto g_k(c)
+  {
+    double cp[n1], cu[n1];
+    int item = -1;
+    for (int x = tid; x < ne * 4 * n1; x += NT) {
+      const int l = x / (4 * n1), rem = x % (4 * n1);
+      const int ft = rem / n1, pp = rem % n1, f = ft + 1;
+      const double* nrm = sN[l][ft];
+      const int nb = sNb[l][f][0], nf = sNb[l][f][2], prow = sNb[l][f][3];
+      const int loc = LOCAL ? sNb[l][f][1] : -1;
+      const double zm = mesh.mat[(e0 + l) * 4 + 2], zp = sZ[l][f];
+      const double* tt = sTT[l] + ft * 2 * n2;
+#pragma unroll
+      for (int k = 0; k < n1; ++k) cp[k] = cu[k] = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) {
+        const int pt = pp + n1 * mm;
+        const double pmv = tt[pt], unm = tt[n2 + pt];
+        double nbp = 0.0, nbun = 0.0;
+        if (nb >= 0) {
+          const int q2 = sPerm[prow + pt];
+          if constexpr (LOCAL) {  // the sibling pyramid is in this workgroup
+            nbp = sTT[loc][(nf - 1) * 2 * n2 + q2];
+            nbun = sTT[loc][(nf - 1) * 2 * n2 + n2 + q2];
+          } else {
+            const double* tp = T2 + (((int64_t)nb * NF + nf) * n2 + q2) * 2;
+            nbp = tp[0];
+            nbun = tp[1];
+          }
+        }
+        double ppv, unp, Fp, Pu;
+        exterior(nb >= 0, nbp, nbun, pmv, unm, mesh.bc, ppv, unp);
+        jump_flux(ppv - pmv, unp - unm, zm, zp, mesh.alpha, ops.wf[f * n2 + pt] * nrm[3], Fp, Pu);
+#pragma unroll
+        for (int k = 0; k < n1; ++k) {
+          cp[k] += sf.Gf[mm * n1 + k] * Fp;
+          cu[k] += sf.Gf[mm * n1 + k] * Pu;
+        }
+      }
+      if (D::kSeparateC) {
+        double* cc = (double*)sCC[l] + ft * 2 * n2;
+#pragma unroll
+        for (int k = 0; k < n1; ++k) {
+          cc[k * n1 + pp] = cp[k];
+          cc[n2 + k * n1 + pp] = cu[k];
+        }
+      } else {
+        item = x;  // at most one item per thread (4 n1 <= n2 <= columns)
+      }
+    }
+    if (!D::kSeparateC) {
+      __syncthreads();  // every trace read before the folded fluxes replace them
+      if (item >= 0) {
+        const int l = item / (4 * n1), rem = item % (4 * n1);
+        const int ft = rem / n1, pp = rem % n1;
+        double* cc = sTT[l] + ft * 2 * n2;
+#pragma unroll
+        for (int k = 0; k < n1; ++k) {
+          cc[k * n1 + pp] = cp[k];
+          cc[n2 + k * n1 + pp] = cu[k];
+        }
+      }
+    }
+  }
+
+  // ---- projection, one field at a time: b-direction, then a-direction with
+  // the triangle lifts, inverse mass, material and the RK stage
+#pragma unroll
+  for (int fld = 0; fld < 4; ++fld) {
+    if (col) {
+#pragma unroll
+      for (int k = 0; k < n1; ++k) sAB[le][k * n2 + m * n1 + p] = bacc[fld][k];
+    }
+    __syncthreads();
+    // D[kj][p] = sum_m l_j(b_m) B[k][m][p]
+    for (int x = tid; x < ne * KJ * n1; x += NT) {
+      const int l = x / (KJ * n1), rem = x % (KJ * n1);
+      const int kj = rem / n1, pp = rem % n1;
+      int k, j;
+      kj_split(kj, k, j);
+      const double* B = sAB[l] + k * n2 + pp;
+      double acc = 0.0;
+      for (int mm = 0; mm < n1; ++mm) acc += sf.La[(k * n1 + mm) * n1 + j] * B[mm * n1];
+      sUD[l][kj * n1 + pp] = acc;
+    }
+    __syncthreads();
+    for (int x = tid; x < ne * Np; x += NT) {
+      const int l = x / Np, n = x % Np;
+      int k = 0;
+      while (kofs(k + 1) <= n) ++k;
+      const int rem = n - kofs(k), j = rem / (k + 1), i = rem % (k + 1);
+      const double* La_k = sf.La + k * n2;  // [p][i]
+      const double* Dk = sUD[l] + (kjofs(k) + j) * n1;
+      const double* cc = D::kSeparateC ? (const double*)sCC[l] : (const double*)sTT[l];
+      const int ty = fld == 0 ? 0 : 1;
+      double v = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
+      for (int pp = 0; pp < n1; ++pp) {
+        const double li = La_k[pp * n1 + i], lj = La_k[pp * n1 + j];
+        v += li * Dk[pp];
+        t1 += lj * cc[0 * 2 * n2 + ty * n2 + k * n1 + pp];
+        t2 += lj * cc[1 * 2 * n2 + ty * n2 + k * n1 + pp];
+        t3 += li * cc[2 * 2 * n2 + ty * n2 + k * n1 + pp];
+        t4 += li * cc[3 * 2 * n2 + ty * n2 + k * n1 + pp];
+      }
+      const double* Le_k = sf.Le + k * 2 * n1;  // [side][i]
+      double s1 = 1.0, s2 = 1.0, s3 = 1.0, s4 = 1.0;
+      if (fld > 0) {
+        s1 = sN[l][0][fld - 1];
+        s2 = sN[l][1][fld - 1];
+        s3 = sN[l][2][fld - 1];
+        s4 = sN[l][3][fld - 1];
+      }
+      v += s1 * Le_k[i] * t1 + s2 * Le_k[n1 + i] * t2 + s3 * Le_k[j] * t3 + s4 * Le_k[n1 + j] * t4;
+      const int64_t el = e0 + l;
+      if (fld == 0) v -= source_term<Np>(mesh, el, n);
+      const double minv = 1.0 / (pyr_jac(sX[l], ops.na[n], ops.nb[n]) * ops.wwc[n]);
+      const double mat = mesh.mat[el * 4 + (fld == 0 ? 0 : 1)];
+      finish_coeff<MODE>(v, minv, mat, out, R, (el * 4 + fld) * Np + n, ra, rb,
+                         dt * mesh.mat[el * 4 + 3]);
+    }
+    __syncthreads();
+  }
+  (void)CREG;
+}
+
+// Resources of a kernel against the device's limits and this file's budgets
+// (checked at setup, before any launch).
+dgpyr_status check_kernel(const void* fn, int threads, const char* name, std::string& msg) {
+  hipFuncAttributes a;
+  hipError_t err = hipFuncGetAttributes(&a, fn);
+  if (err != hipSuccess) {
+    msg = std::string("hipFuncGetAttributes(") + name + "): " + hipGetErrorString(err);
+    return DGPYR_E_HIP;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  err = hipGetDevice(&dev);
+  if (err == hipSuccess) err = hipGetDeviceProperties(&prop, dev);
+  if (err != hipSuccess) {
+    msg = std::string("device properties: ") + hipGetErrorString(err);
+    return DGPYR_E_HIP;
+  }
+  if (a.sharedSizeBytes > (size_t)kLdsBudget || a.sharedSizeBytes > prop.sharedMemPerBlock ||
+      a.localSizeBytes > kPrivateBudget || a.maxThreadsPerBlock < threads) {
+    msg = std::string(name) + ": " + std::to_string(a.sharedSizeBytes) + " bytes of LDS (device " +
+          std::to_string(prop.sharedMemPerBlock) + "), " + std::to_string(a.localSizeBytes) +
+          " bytes of private memory per lane, " + std::to_string(threads) + " threads (at most " +
+          std::to_string(a.maxThreadsPerBlock) + ")";
+    return DGPYR_E_UNSUPPORTED;
+  }
+  return DGPYR_OK;
+}
+
+template <int N>
+dgpyr_status check_n(const dgpyr_ctx& c, std::string& msg) {
+  dgpyr_status st;
+  if constexpr (SfDims<N>::hex_elems() > 0) {
+    if (c.sf_local) {
+      if ((st = check_kernel((const void*)k_sf_trace<N, 1>, TraceShape<N, 1>::THREADS,
+                             "k_sf_trace", msg)))
+        return st;
+      if ((st = check_kernel((const void*)k_sf_stage<N, 0, true>, SfShape<N, true>::THREADS,
+                             "k_sf_stage", msg)))
+        return st;
+      return check_kernel((const void*)k_sf_stage<N, 1, true>, SfShape<N, true>::THREADS,
+                          "k_sf_stage", msg);
+    }
+  }
+  if ((st = check_kernel((const void*)k_sf_trace<N, 5>, TraceShape<N, 5>::THREADS, "k_sf_trace",
+                         msg)))
+    return st;
+  if ((st = check_kernel((const void*)k_sf_stage<N, 0, false>, SfShape<N, false>::THREADS,
+                         "k_sf_stage", msg)))
+    return st;
+  return check_kernel((const void*)k_sf_stage<N, 1, false>, SfShape<N, false>::THREADS,
+                      "k_sf_stage", msg);
+}
+
+template <int N>
+hipError_t trace_n(const dgpyr_ctx& c, const double* U, double* T2, hipStream_t s) {
+  if (c.sf_local) {
+    if constexpr (SfDims<N>::hex_elems() > 0) {
+      using TS = TraceShape<N, 1>;
+      hipLaunchKernelGGL((k_sf_trace<N, 1>), dim3((unsigned)((c.K + TS::E - 1) / TS::E)),
+                         dim3(TS::THREADS), 0, s, U, T2, c.sf, c.ops, c.mesh.verts, c.K);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else {
+    using TS = TraceShape<N, 5>;
+    hipLaunchKernelGGL((k_sf_trace<N, 5>), dim3((unsigned)((c.K + TS::E - 1) / TS::E)),
+                       dim3(TS::THREADS), 0, s, U, T2, c.sf, c.ops, c.mesh.verts, c.K);
+  }
+  return hipGetLastError();
+}
+
+template <int N, bool LOCAL>
+hipError_t stage_nl(const dgpyr_ctx& c, int mode, const double* U, const double* T2, double* out,
+                    double* R, double ra, double rb, double dt, hipStream_t s) {
+  using SS = SfShape<N, LOCAL>;
+  const dim3 grid((unsigned)((c.K + SS::E - 1) / SS::E)), block(SS::THREADS);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_sf_stage<N, 0, LOCAL>), grid, block, 0, s, U, T2, c.sf, c.ops, c.mesh,
+                       out, R, ra, rb, dt);
+  else
+    hipLaunchKernelGGL((k_sf_stage<N, 1, LOCAL>), grid, block, 0, s, U, T2, c.sf, c.ops, c.mesh,
+                       out, R, ra, rb, dt);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t stage_n(const dgpyr_ctx& c, int mode, const double* U, const double* T2, double* out,
+                   double* R, double ra, double rb, double dt, hipStream_t s) {
+  if constexpr (SfDims<N>::hex_elems() > 0) {
+    if (c.sf_local) return stage_nl<N, true>(c, mode, U, T2, out, R, ra, rb, dt, s);
+  }
+  if (c.sf_local) return hipErrorInvalidValue;
+  return stage_nl<N, false>(c, mode, U, T2, out, R, ra, rb, dt, s);
+}
+
+template <int N>
+bool local_possible() {
+  return SfDims<N>::hex_elems() > 0;
+}
+
+}  // namespace
+
+#define DGPYR_DISPATCH_SF(fn, fail, ...) \
+  switch (c.N) {                        \
+    case 0: return fn<0>(__VA_ARGS__);  \
+    case 1: return fn<1>(__VA_ARGS__);  \
+    case 2: return fn<2>(__VA_ARGS__);  \
+    case 3: return fn<3>(__VA_ARGS__);  \
+    case 4: return fn<4>(__VA_ARGS__);  \
+    case 5: return fn<5>(__VA_ARGS__);  \
+    case 6: return fn<6>(__VA_ARGS__);  \
+    case 7: return fn<7>(__VA_ARGS__);  \
+    case 8: return fn<8>(__VA_ARGS__);  \
+    default: return fail;               \
+  }
+
+bool sf_local_possible(const dgpyr_ctx& c) { DGPYR_DISPATCH_SF(local_possible, false, ) }
+
+dgpyr_status sf_check_resources(const dgpyr_ctx& c, std::string& msg) {
+  DGPYR_DISPATCH_SF(check_n, DGPYR_E_ORDER, c, msg)
+}
+
+hipError_t launch_sf_trace(const dgpyr_ctx& c, const double* U, double* T2, hipStream_t s) {
+  DGPYR_DISPATCH_SF(trace_n, hipErrorInvalidValue, c, U, T2, s)
+}
+
+hipError_t launch_sf_stage(const dgpyr_ctx& c, int mode, const double* U, const double* T2,
+                           double* out, double* R, double ra, double rb, double dt, hipStream_t s) {
+  DGPYR_DISPATCH_SF(stage_n, hipErrorInvalidValue, c, mode, U, T2, out, R, ra, rb, dt, s)
+}
+
+}  // namespace dgpyr

@@ -36,11 +36,3 @@ def rel_err_per_field(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
     fmax = np.abs(ref).max(axis=(0, 2))
     den = np.maximum(fmax, max(1e-3 * fmax.max(), 1e-300))
     return num / den
-
-
-# Kernels held back from device runs: a device fault occurred in a combined run
-# that included them and has not been explained.  Their memory accesses pass a
-# guarded CPU emulation of the library; they return to the device suite once a
-# run limited to them has passed.
-HELD_BACK = pytest.mark.skip(
-    reason="held back from device runs after an unexplained device fault in a combined run")

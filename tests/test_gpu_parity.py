@@ -8,7 +8,7 @@ canonical coefficient layout; LSRK trajectories within 1e-11.
 import numpy as np
 import pytest
 
-from gpu_helpers import HELD_BACK, gpu_rhs, log, rel_err_per_field
+from gpu_helpers import gpu_rhs, log, rel_err_per_field
 from oracle import AcousticDG, lsrk_run
 from oracle.dg import wall_mode
 from synth import hex_pyramid_mesh, octahedron_mesh, random_materials, random_state, single_pyramid
@@ -24,9 +24,10 @@ def _solver(xyz, e2v, N, **kw):
 
 
 PATHS = {"mfma": {}, "sumfact": {"sum_factorized": True}}
-# The sum-factorised kernels are disabled in the device build (setup returns
-# E_UNSUPPORTED); their parametrisations stay in the suite, skipped.
-PATH_PARAMS = [pytest.param("mfma"), pytest.param("sumfact", marks=HELD_BACK)]
+# matrix-core dense operators, and the sum-factorised kernels (whole
+# hexahedra per workgroup where the mesh allows, N <= 6; otherwise traces of
+# all faces through HBM)
+PATH_PARAMS = [pytest.param("mfma"), pytest.param("sumfact")]
 # 4-element groups per wave exercised per path (the fused matrix-core kernels
 # take 1 or 2; 0 = the library's default).
 GROUPS = {"mfma": (1, 2), "sumfact": (0,)}

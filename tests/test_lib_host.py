@@ -146,9 +146,9 @@ def test_setup_errors_before_device(B):
     with pytest.raises(dg.DgpyrError) as ex:
         dg.Solver(xyz, e2v, 2, precision="split_bf16", alpha=-1.0)
     assert ex.value.status in (B.E_ARG, B.E_UNSUPPORTED)
-    # the sum-factorised kernels are not enabled in the device build
+    # the sum-factorised kernels are FP64 only
     with pytest.raises(dg.DgpyrError) as ex:
-        dg.Solver(xyz, e2v, 2, sum_factorized=True)
+        dg.Solver(xyz, e2v, 2, sum_factorized=True, precision="fp32_mfma")
     assert ex.value.status == B.E_UNSUPPORTED
     # batch arguments are checked before any device work
     with pytest.raises(dg.DgpyrError) as ex:
