@@ -71,26 +71,28 @@ def sf_work(name: str, N: int, local: bool = True):
     kernel: the multiply-adds of its one-dimensional contractions (a-, b- and
     c-directions), pointwise metric and fluxes, and the FP64 data it must move
     with traces kept as (p, u.n) pairs -- base faces only when whole
-    hexahedra share a workgroup (local), all five faces otherwise."""
+    hexahedra share a workgroup (local); otherwise the four-field traces of
+    all five faces from the matrix-core trace kernel."""
     n1 = N + 1
     n2, Np, KJ = n1 * n1, n_basis(N), n1 * (n1 + 1) // 2
     if name == "trace":
-        fma = 4 * n1 * (Np + KJ + n1 * KJ)
-        if not local:
-            fma += 16 * n1 * (Np + KJ + n2)
-        return 2 * fma, 32 * Np + (16 if local else 80) * n2
+        if not local:  # the matrix-core trace kernel, four fields at every face point
+            return kernel_work("trace", N)
+        return 2 * 4 * n1 * (Np + KJ + n1 * KJ), 32 * Np + 16 * n2
     if name == "stage":
         per_field = (2 * n1 * Np + 4 * n1 * (Np + KJ + n2) + n2 * (3 * KJ + 3 * n2 + 3 * n1)
                      + KJ * n2 + 5 * n1 * Np)
         fma = (4 * per_field + n2 * (9 * n1 + 3 * n2) + 3 * n2 * n1 + n2 * (n2 + 4 * n1)
                + 8 * n1 * n2)
-        return 2 * fma, 128 * Np + (16 if local else 80) * n2 + 152
+        return 2 * fma, 128 * Np + (16 if local else 160) * n2 + 152
     raise KeyError(name)
 
 
 def work(name: str, N: int, path: str = "fused"):
     """Per-element work of one launch of kernel ``name`` on kernel path ``path``."""
-    return sf_work(name, N) if path == "sumfact" else kernel_work(name, N)
+    # the sum-factorised stage owns whole hexahedra up to N = 6 (the bench
+    # meshes come in hexahedra), else it reads all-face traces
+    return sf_work(name, N, local=N <= 6) if path == "sumfact" else kernel_work(name, N)
 
 
 def stage_work(N: int):

@@ -19,6 +19,16 @@ constexpr int kEW = 4;
 constexpr int kEB = kWaves * kEW;
 constexpr int kBlock = 64 * kWaves;
 
+// Orders this wave's LDS writes before its later LDS reads (and reads before
+// later writes): the transpose tile sQ[wv] is private to its wave and a
+// wave's LDS operations complete in issue order, so no workgroup barrier is
+// needed; the fences keep the compiler from moving LDS accesses across.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ bfx8 load_bf8(const uint16_t* p) {
   return *reinterpret_cast<const bfx8*>(p);
 }
@@ -52,16 +62,28 @@ struct Bf16Waves {
   static constexpr int value = N >= 6 ? 2 : 1;
 };
 
+// Unit face normals and surface Jacobians of the workgroup's elements in LDS
+// ((N+1)^2 base points + 4 planar triangles per element), where they fit
+// next to the transpose tiles under 56 KiB.
+template <int N>
+struct Bf16Norm {
+  static constexpr int Nfq = (N + 1) * (N + 1);
+  static constexpr int base = kEB * 16 * 8 + kWaves * 16 * 33 * 8 + kEB * 5 * 24 + 10 * Nfq * 4;
+  static constexpr bool value = base + kEB * (Nfq + 4) * 4 * 8 <= 56 * 1024;
+};
+
 template <int N, int MODE>
 __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(const double* U,
                                                        const double* __restrict__ T, Bf16Ops bo,
                                                        DevOps ops, DevMesh mesh, double* out,
                                                        double* R, double ra, double rb, double dt) {
   using TT = Tiles<N>;
+  constexpr bool kNorm = Bf16Norm<N>::value;
   __shared__ double sX[kEB][16];
   __shared__ double sQ[kWaves][16][33];
   __shared__ FaceNb sNb[kEB][5];
   __shared__ int sPerm[10 * TT::Nfq];
+  __shared__ double sN[kNorm ? kEB : 1][kNorm ? TT::Nfq + 4 : 1][4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t eb0 = (int64_t)blockIdx.x * kEB;
   for (int x = threadIdx.x; x < kEB * 16; x += kBlock) {
@@ -106,6 +128,16 @@ __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(cons
     }
   }
   __syncthreads();
+  if (kNorm) {
+    // rows 0 .. Nfq-1: base points; Nfq + f - 1: triangle f = 1..4
+    for (int x = threadIdx.x; x < kEB * (TT::Nfq + 4); x += kBlock) {
+      const int le = x / (TT::Nfq + 4), r = x - le * (TT::Nfq + 4);
+      const int f = r < TT::Nfq ? 0 : r - TT::Nfq + 1;
+      const int q = r < TT::Nfq ? r : f * TT::Nfq;
+      face_normal_unit(sX[le], f, ops.fa[q], ops.fb[q], sN[le][r]);
+    }
+    __syncthreads();
+  }
   const double* xv = sX[wv * kEW + de];
   fx4 z[TT::NIT];
 #pragma unroll
@@ -147,7 +179,7 @@ __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(cons
 #pragma unroll
       for (int v = 0; v < 4; ++v) sQ[wv][4 * de + v][16 * sub + dq] = Q[v];
     }
-    __syncthreads();
+    wave_lds_sync();
     bfx8 qh, ql;
     split8(&sQ[wv][row][8 * kq], qh, ql);
 #pragma unroll
@@ -155,7 +187,7 @@ __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(cons
       const size_t fo = (((size_t)t32 * TT::NIT + u) * 64 + lane) * 8;
       z[u] = mma_bf16x3(qh, ql, load_bf8(bo.VH + fo), load_bf8(bo.VL + fo), z[u]);
     }
-    __syncthreads();
+    wave_lds_sync();
   }
 
   // surface (Algorithm 2): fluxes of 32 face points per chunk; the traces of
@@ -192,14 +224,20 @@ __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(cons
       const int q = 32 * t32 + 16 * sub + dq;
       double F[4] = {0.0, 0.0, 0.0, 0.0};
       if (e < mesh.K && q < TT::Nfc) {
-        double nr[4];
-        face_normal_unit(xv, q / TT::Nfq, ops.fa[q], ops.fb[q], nr);
-        flux_from_traces(cur[sub], mesh, zm, nr[0], nr[1], nr[2], ops.wf[q] * nr[3], F);
+        const int f = q / TT::Nfq;
+        if (kNorm) {
+          const double* nr = sN[wv * kEW + de][f == 0 ? q : TT::Nfq + f - 1];
+          flux_from_traces(cur[sub], mesh, zm, nr[0], nr[1], nr[2], ops.wf[q] * nr[3], F);
+        } else {
+          double nr[4];
+          face_normal_unit(xv, f, ops.fa[q], ops.fb[q], nr);
+          flux_from_traces(cur[sub], mesh, zm, nr[0], nr[1], nr[2], ops.wf[q] * nr[3], F);
+        }
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) sQ[wv][4 * de + v][16 * sub + dq] = F[v];
     }
-    __syncthreads();
+    wave_lds_sync();
     bfx8 fh, fl;
     split8(&sQ[wv][row][8 * kq], fh, fl);
 #pragma unroll
@@ -207,7 +245,7 @@ __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(cons
       const size_t fo = (((size_t)t32 * TT::NIT + u) * 64 + lane) * 8;
       z[u] = mma_bf16x3(fh, fl, load_bf8(bo.LfH + fo), load_bf8(bo.LfL + fo), z[u]);
     }
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub) cur[sub] = nxt[sub];
   }

@@ -24,8 +24,10 @@
 // hexahedron pair their four triangle faces among themselves; when the mesh
 // comes in such groups a workgroup owns whole hexahedra and exchanges the
 // triangle traces in LDS, and only the quadrilateral base traces go through
-// HBM (written by k_sf_trace).  Otherwise k_sf_trace writes the traces of all
-// five faces and the stage reads its neighbours' from HBM.
+// HBM (written by k_sf_trace).  Otherwise (general meshes, and N = 7, 8 where
+// six elements do not fit a workgroup) the traces of all five faces come from
+// the FP64 matrix-core trace kernel in the [K][Nfc][4] layout and the stage
+// reads its neighbours' from HBM.
 //
 // Work shape.  A workgroup owns E elements and one thread per (element, a, b)
 // column.  The four fields are processed one at a time through LDS: the
@@ -79,7 +81,11 @@ struct SfDims {
   static constexpr int kTables = 16 + 16 + 5 + 10;  // vertices, normals, rho c, ints
   static constexpr int PER_ELEM = kTables + UD + AB + TT + CC;
   static constexpr int PERM_BYTES = 10 * n2 * 4;
-  static constexpr int bytes(int E) { return E * PER_ELEM * 8 + PERM_BYTES; }
+  // one-dimensional factors read with lane-dependent indices, staged in LDS
+  // once per workgroup: l^k_i(x_p), d/da l^k_i(x_p) [k][p][i], l^k_i(-1, +1)
+  // [k][s][i]
+  static constexpr int TAB = 2 * n3 + 2 * n2;
+  static constexpr int bytes(int E) { return E * PER_ELEM * 8 + PERM_BYTES + TAB * 8; }
   // elements per workgroup when hexahedra (6 elements) are kept whole, 0 if
   // not even one fits; at most 512 columns
   static constexpr int hex_elems() {
@@ -139,19 +145,71 @@ __device__ __forceinline__ void exterior(bool inner, double nbp, double nbun, do
 }
 
 // ---------------------------------------------------------------------------
-// Traces: (p, u.n) at the base points (NF = 1) or at the points of all five
-// faces (NF = 5) of every element, T2[K][NF][n2][2].  One thread per
-// (element, face, a-index p) evaluates the n1 points of its line through the
-// a-direction contraction shared by them.
+// Base traces (p, u.n) of every element, T2[K][n2][2] (NF = 1), one thread per
+// face point; the state of the workgroup's elements and the one-dimensional
+// factors are staged in LDS.
 template <int N, int NF>
 struct TraceShape {
   using D = SfDims<N>;
-  static constexpr int per_elem = 4 * D::Np + 2 * NF * D::n2;  // doubles
-  static constexpr int E = (40 * 1024) / (per_elem * 8) < 1 ? 1
-                           : (40 * 1024) / (per_elem * 8) > 32 ? 32
-                                                                : (40 * 1024) / (per_elem * 8);
-  static constexpr int THREADS = round64(E * NF * D::n1);
+  static constexpr int PTS = NF * D::n2;  // points per element
+  static constexpr int E = 256 / PTS < 1 ? 1 : (256 / PTS > 64 ? 64 : 256 / PTS);
+  static constexpr int THREADS = round64(E * PTS);
 };
+
+// Stages the one-dimensional factors of the basis into LDS (La, Da [k][p][i],
+// Le [k][s][i]).
+template <int N>
+__device__ __forceinline__ void stage_tables(const SfOps& sf, double* sLa, double* sDa, double* sLe,
+                                             int tid, int nt) {
+  constexpr int n1 = N + 1, n3 = n1 * n1 * n1;
+  for (int x = tid; x < n3; x += nt) {
+    sLa[x] = sf.La[x];
+    sDa[x] = sf.Da[x];
+  }
+  for (int x = tid; x < 2 * n1 * n1; x += nt) sLe[x] = sf.Le[x];
+}
+
+// Value of field u (coefficients of one element) at point pt = p + n1 m of
+// face f: base (f = 0) at (a_p, b_m, -1); a = -1, +1 (f = 1, 2) at
+// (b_p, c_m); b = -1, +1 (f = 3, 4) at (a_p, c_m) (c_m the Gauss-Jacobi(1,0)
+// nodes).
+template <int N>
+__device__ __forceinline__ double face_value(const double* u, int f, int p, int m, const SfOps& sf,
+                                             const double* sLa, const double* sLe) {
+  constexpr int n1 = N + 1;
+  double val = 0.0;
+#pragma unroll
+  for (int k = 0; k <= N; ++k) {
+    const double* uk = u + kofs(k);
+    const double* La_p = sLa + (k * n1 + p) * n1;
+    double Y = 0.0;
+    if (f == 0) {
+      const double* La_m = sLa + (k * n1 + m) * n1;
+      // rows j one at a time: unrolled, the compiler loads all coefficients
+      // ahead and needs more registers than the kernel has
+#pragma unroll 1
+      for (int j = 0; j <= k; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i <= k; ++i) acc += La_p[i] * uk[j * (k + 1) + i];
+        Y += La_m[j] * acc;
+      }
+      val += sf.Gb[k] * Y;
+    } else {
+      const double* Le_s = sLe + (k * 2 + ((f == 2 || f == 4) ? 1 : 0)) * n1;
+      const bool afc = f <= 2;  // a = -1/+1: the a-factor at the face, b at the edge point
+#pragma unroll
+      for (int j = 0; j <= k; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i <= k; ++i) acc += (afc ? Le_s[i] : La_p[i]) * uk[j * (k + 1) + i];
+        Y += (afc ? La_p[j] : Le_s[j]) * acc;
+      }
+      val += sf.Gf[m * n1 + k] * Y;
+    }
+  }
+  return val;
+}
 
 template <int N, int NF>
 __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
@@ -159,110 +217,41 @@ __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
     const double* __restrict__ verts, int64_t K) {
   using D = SfDims<N>;
   using TS = TraceShape<N, NF>;
-  constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, E = TS::E, NT = TS::THREADS;
+  constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, E = TS::E, NT = TS::THREADS, PTS = TS::PTS;
   __shared__ double sU[E][4 * Np];
-  __shared__ double sO[E][NF * n2 * 2];
   __shared__ double sX[E][16];
+  __shared__ double sLa[D::n3], sDa[D::n3], sLe[2 * n2];
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(K - e0 < E ? K - e0 : E);
   for (int x = tid; x < ne * 4 * Np; x += NT) sU[x / (4 * Np)][x % (4 * Np)] = U[e0 * 4 * Np + x];
   for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
+  stage_tables<N>(sf, sLa, sDa, sLe, tid, NT);
   __syncthreads();
-  for (int x = tid; x < ne * NF * n1; x += NT) {
-    const int le = x / (NF * n1), rem = x % (NF * n1);
-    const int f = rem / n1, p = rem % n1;
-    const double* xv = sX[le];
-    double outp[n1], outu[n1];
-#pragma unroll
-    for (int m = 0; m < n1; ++m) outp[m] = outu[m] = 0.0;
-    double tn[3] = {0.0, 0.0, 0.0};
-    if (f > 0) {  // planar triangle: one unit normal
-      double nr[4];
-      face_normal_unit(xv, f, ops.fa[f * n2], ops.fb[f * n2], nr);
-      tn[0] = nr[0];
-      tn[1] = nr[1];
-      tn[2] = nr[2];
-    }
+  for (int x = tid; x < ne * PTS; x += NT) {
+    const int le = x / PTS, q = x % PTS;
+    const int f = q / n2, pt = q % n2, p = pt % n1, m = pt / n1;
+    double nr[4];
+    if (f == 0) face_normal_unit(sX[le], 0, ops.xg[p], ops.xg[m], nr);
+    else face_normal_unit(sX[le], f, ops.fa[f * n2], ops.fb[f * n2], nr);
+    double outp = 0.0, outu = 0.0;
 #pragma unroll
     for (int fld = 0; fld < 4; ++fld) {
-      const double* u = sU[le] + fld * Np;
-      double val[n1];
-#pragma unroll
-      for (int m = 0; m < n1; ++m) val[m] = 0.0;
-#pragma unroll
-      for (int k = 0; k <= N; ++k) {
-        const double* uk = u + kofs(k);
-        if (f == 0) {
-          // base (c = -1): g_k(-1) sum_j l_j(b_m) sum_i l_i(a_p) u_ijk
-          const double* La_p = sf.La + (k * n1 + p) * n1;
-          double A[n1];
-#pragma unroll
-          for (int j = 0; j <= k; ++j) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i <= k; ++i) acc += La_p[i] * uk[j * (k + 1) + i];
-            A[j] = sf.Gb[k] * acc;
-          }
-#pragma unroll
-          for (int m = 0; m < n1; ++m) {
-            const double* La_m = sf.La + (k * n1 + m) * n1;
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j <= k; ++j) acc += La_m[j] * A[j];
-            val[m] += acc;
-          }
-        } else {
-          // a = -1 / +1 (f = 1 / 2): sum_j l_j(sigma_p) sum_i l_i(-+1) u_ijk;
-          // b = -1 / +1 (f = 3 / 4): sum_j l_j(-+1) sum_i l_i(sigma_p) u_ijk;
-          // then g_k at the Gauss-Jacobi(1,0) nodes c_m
-          const double* La_p = sf.La + (k * n1 + p) * n1;
-          const double* Le_s = sf.Le + (k * 2 + ((f == 2 || f == 4) ? 1 : 0)) * n1;
-          double Y = 0.0;
-#pragma unroll
-          for (int j = 0; j <= k; ++j) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i <= k; ++i) acc += (f <= 2 ? Le_s[i] : La_p[i]) * uk[j * (k + 1) + i];
-            Y += (f <= 2 ? La_p[j] : Le_s[j]) * acc;
-          }
-#pragma unroll
-          for (int m = 0; m < n1; ++m) val[m] += sf.Gf[m * n1 + k] * Y;
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < n1; ++m) {
-        if (fld == 0) {
-          outp[m] = val[m];
-        } else {
-          double nd = tn[fld - 1];
-          if (f == 0) {  // the base normal varies with (a, b)
-            double nr[4];
-            face_normal_unit(xv, 0, ops.xg[p], ops.xg[m], nr);
-            nd = nr[fld - 1];
-          }
-          outu[m] += nd * val[m];
-        }
-      }
+      const double v = face_value<N>(sU[le] + fld * Np, f, p, m, sf, sLa, sLe);
+      const double nd = fld == 1 ? nr[0] : fld == 2 ? nr[1] : nr[2];
+      if (fld == 0) outp = v;
+      else outu += nd * v;
     }
-#pragma unroll
-    for (int m = 0; m < n1; ++m) {
-      const int pt = f * n2 + p + n1 * m;
-      sO[le][2 * pt + 0] = outp[m];
-      sO[le][2 * pt + 1] = outu[m];
-    }
+    T2[(e0 * PTS + x) * 2 + 0] = outp;  // row of element e0 + le, point q
+    T2[(e0 * PTS + x) * 2 + 1] = outu;
   }
-  __syncthreads();
-  // coalesced store: the block's rows are contiguous in T2
-  for (int x = tid; x < ne * NF * n2 * 2; x += NT)
-    T2[e0 * NF * n2 * 2 + x] = sO[x / (NF * n2 * 2)][x % (NF * n2 * 2)];
 }
 
 // ---------------------------------------------------------------------------
 // Fused stage.  LOCAL: workgroups own whole hexahedra (triangle neighbours
-// are in the workgroup, T2 holds base traces only); otherwise T2 holds the
-// traces of all five faces and triangle neighbours outside the workgroup are
-// read from it.
+// are in the workgroup, T2 holds (p, u.n) base traces only); otherwise T2 is
+// the four-field trace array [K][Nfc][4] of all five faces, from which the
+// neighbour's p and n.u are read.
 template <int N, int MODE, bool LOCAL>
 __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
     const double* U, const double* __restrict__ T2, SfOps sf, DevOps ops, DevMesh mesh,
@@ -270,7 +259,6 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
   using D = SfDims<N>;
   constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, KJ = D::KJ;
   constexpr int E = SfShape<N, LOCAL>::E, NT = SfShape<N, LOCAL>::THREADS;
-  constexpr int NF = LOCAL ? 1 : 5;  // faces per element row of T2
   constexpr int CREG = D::kSeparateC ? D::CC : D::TT;
   __shared__ double sX[E][16];
   __shared__ double sN[E][4][4];   // triangle faces 1..4: unit normal, sJ
@@ -281,11 +269,14 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
   __shared__ double sTT[E][D::TT];
   __shared__ double sCC[D::kSeparateC ? E : 1][D::kSeparateC ? D::CC : 1];
   __shared__ int sPerm[10 * n2];
+  __shared__ double sLa[D::n3], sDa[D::n3], sLe[2 * n2];
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(mesh.K - e0 < E ? mesh.K - e0 : E);
 
-  // ---- tables: vertices, face neighbours, triangle normals, permutations
+  // ---- tables: vertices, face neighbours, triangle normals, permutations,
+  // one-dimensional factors
+  stage_tables<N>(sf, sLa, sDa, sLe, tid, NT);
   for (int x = tid; x < E * 16; x += NT) {
     const int le = x / 16;
     sX[le][x % 16] = le < ne ? mesh.verts[(e0 + le) * 16 + x % 16] : 0.0;
@@ -352,12 +343,15 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
       int k, j;
       kj_split(kj, k, j);
       const double* u = sUD[l] + kofs(k) + j * (k + 1);
-      const double* La = sf.La + (k * n1 + pp) * n1;
-      const double* Da = sf.Da + (k * n1 + pp) * n1;
+      const double* La = sLa + (k * n1 + pp) * n1;
+      const double* Da = sDa + (k * n1 + pp) * n1;
       double a = 0.0, ad = 0.0;
-      for (int i = 0; i <= k; ++i) {
-        a += La[i] * u[i];
-        ad += Da[i] * u[i];
+#pragma unroll
+      for (int i = 0; i < n1; ++i) {
+        if (i <= k) {
+          a += La[i] * u[i];
+          ad += Da[i] * u[i];
+        }
       }
       sAB[l][kj * n1 + pp] = a;
       sAB[l][KJ * n1 + kj * n1 + pp] = ad;
@@ -366,18 +360,18 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
     for (int x = tid; x < ne * 4 * n1; x += NT) {
       const int l = x / (4 * n1), rem = x % (4 * n1);
       const int ft = rem / n1, pp = rem % n1, f = ft + 1;
-      const double* Le_s = sf.Le + ((f == 2 || f == 4) ? 1 : 0) * n1;
+      const double* Le_s = sLe + ((f == 2 || f == 4) ? 1 : 0) * n1;
       double val[n1];
 #pragma unroll
       for (int mm = 0; mm < n1; ++mm) val[mm] = 0.0;
 #pragma unroll
       for (int k = 0; k <= N; ++k) {
         const double* uk = sUD[l] + kofs(k);
-        const double* La_p = sf.La + (k * n1 + pp) * n1;
+        const double* La_p = sLa + (k * n1 + pp) * n1;
         const double* Le_k = Le_s + k * 2 * n1;
         double Y = 0.0;
-#pragma unroll
-        for (int j = 0; j <= k; ++j) {
+#pragma unroll 1
+        for (int j = 0; j <= k; ++j) {  // rows one at a time (register pressure)
           double acc = 0.0;
 #pragma unroll
           for (int i = 0; i <= k; ++i) acc += (f <= 2 ? Le_k[i] : La_p[i]) * uk[j * (k + 1) + i];
@@ -402,11 +396,11 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
       double s0[n1], sa[n1], sb[n1];
 #pragma unroll
       for (int k = 0; k < n1; ++k) {
-        const double* La_m = sf.La + (k * n1 + m) * n1;
-        const double* Da_m = sf.Da + (k * n1 + m) * n1;
+        const double* La_m = sLa + (k * n1 + m) * n1;
+        const double* Da_m = sDa + (k * n1 + m) * n1;
         double x0 = 0.0, xa = 0.0, xb = 0.0;
-#pragma unroll
-        for (int j = 0; j <= k; ++j) {
+#pragma unroll 1
+        for (int j = 0; j <= k; ++j) {  // one row at a time (register pressure)
           const double A = sAB[le][(kjofs(k) + j) * n1 + p];
           const double Ad = sAB[le][KJ * n1 + (kjofs(k) + j) * n1 + p];
           x0 += La_m[j] * A;
@@ -462,9 +456,15 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
     double nbp = 0.0, nbun = 0.0;
     if (nb >= 0) {
       const int q2 = sPerm[sNb[le][0][3] + pm];
-      const double* tp = T2 + (((int64_t)nb * NF + sNb[le][0][2]) * n2 + q2) * 2;
-      nbp = tp[0];
-      nbun = tp[1];
+      if constexpr (LOCAL) {  // (p, u.n') pairs
+        const double* tp = T2 + ((int64_t)nb * n2 + q2) * 2;
+        nbp = tp[0];
+        nbun = tp[1];
+      } else {  // four fields
+        const double* tp = T2 + ((int64_t)nb * D::Nfc + sNb[le][0][2] * n2 + q2) * 4;
+        nbp = tp[0];
+        nbun = -(nr[0] * tp[1] + nr[1] * tp[2] + nr[2] * tp[3]);
+      }
     }
     double pp, unp, Fp, Pu;
     exterior(nb >= 0, nbp, nbun, pmv, unm, mesh.bc, pp, unp);
@@ -505,9 +505,9 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
             nbp = sTT[loc][(nf - 1) * 2 * n2 + q2];
             nbun = sTT[loc][(nf - 1) * 2 * n2 + n2 + q2];
           } else {
-            const double* tp = T2 + (((int64_t)nb * NF + nf) * n2 + q2) * 2;
+            const double* tp = T2 + ((int64_t)nb * D::Nfc + nf * n2 + q2) * 4;
             nbp = tp[0];
-            nbun = tp[1];
+            nbun = -(nrm[0] * tp[1] + nrm[1] * tp[2] + nrm[2] * tp[3]);
           }
         }
         double ppv, unp, Fp, Pu;
@@ -562,7 +562,8 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
       kj_split(kj, k, j);
       const double* B = sAB[l] + k * n2 + pp;
       double acc = 0.0;
-      for (int mm = 0; mm < n1; ++mm) acc += sf.La[(k * n1 + mm) * n1 + j] * B[mm * n1];
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) acc += sLa[(k * n1 + mm) * n1 + j] * B[mm * n1];
       sUD[l][kj * n1 + pp] = acc;
     }
     __syncthreads();
@@ -571,11 +572,12 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
       int k = 0;
       while (kofs(k + 1) <= n) ++k;
       const int rem = n - kofs(k), j = rem / (k + 1), i = rem % (k + 1);
-      const double* La_k = sf.La + k * n2;  // [p][i]
+      const double* La_k = sLa + k * n2;  // [p][i]
       const double* Dk = sUD[l] + (kjofs(k) + j) * n1;
       const double* cc = D::kSeparateC ? (const double*)sCC[l] : (const double*)sTT[l];
       const int ty = fld == 0 ? 0 : 1;
       double v = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
+#pragma unroll
       for (int pp = 0; pp < n1; ++pp) {
         const double li = La_k[pp * n1 + i], lj = La_k[pp * n1 + j];
         v += li * Dk[pp];
@@ -584,7 +586,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
         t3 += li * cc[2 * 2 * n2 + ty * n2 + k * n1 + pp];
         t4 += li * cc[3 * 2 * n2 + ty * n2 + k * n1 + pp];
       }
-      const double* Le_k = sf.Le + k * 2 * n1;  // [side][i]
+      const double* Le_k = sLe + k * 2 * n1;  // [side][i]
       double s1 = 1.0, s2 = 1.0, s3 = 1.0, s4 = 1.0;
       if (fld > 0) {
         s1 = sN[l][0][fld - 1];
@@ -648,9 +650,6 @@ dgpyr_status check_n(const dgpyr_ctx& c, std::string& msg) {
                           "k_sf_stage", msg);
     }
   }
-  if ((st = check_kernel((const void*)k_sf_trace<N, 5>, TraceShape<N, 5>::THREADS, "k_sf_trace",
-                         msg)))
-    return st;
   if ((st = check_kernel((const void*)k_sf_stage<N, 0, false>, SfShape<N, false>::THREADS,
                          "k_sf_stage", msg)))
     return st;
@@ -669,9 +668,7 @@ hipError_t trace_n(const dgpyr_ctx& c, const double* U, double* T2, hipStream_t 
       return hipErrorInvalidValue;
     }
   } else {
-    using TS = TraceShape<N, 5>;
-    hipLaunchKernelGGL((k_sf_trace<N, 5>), dim3((unsigned)((c.K + TS::E - 1) / TS::E)),
-                       dim3(TS::THREADS), 0, s, U, T2, c.sf, c.ops, c.mesh.verts, c.K);
+    return launch_trace_mfma(c, U, T2, s);  // four-field traces of all five faces
   }
   return hipGetLastError();
 }

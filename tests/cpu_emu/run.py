@@ -7,6 +7,8 @@ indexing and its results can be checked without a GPU.  Test infrastructure
 only.
 
     python tests/cpu_emu/run.py --k1d 40 --N 4    # one right-hand side on a mesh
+    python tests/cpu_emu/run.py --k1d 64 --N 5 --edge-blocks 64
+        # the first and last 64 workgroups of each launch only (index check)
 """
 
 from __future__ import annotations
@@ -48,7 +50,7 @@ def build(force: bool = False) -> str:
 
 
 def run(xyz, e2v, N, U, rho=None, kappa=None, bc="wall", alpha=1.0, nsteps=0, dt=0.0,
-        timeout=3600):
+        timeout=3600, edge_blocks=0):
     """Right-hand side (nsteps = 0) or the state after nsteps LSRK steps,
     shape (K, 4, Np), and whether the whole-hexahedron variant ran."""
     exe = build()
@@ -68,6 +70,8 @@ def run(xyz, e2v, N, U, rho=None, kappa=None, bc="wall", alpha=1.0, nsteps=0, dt
             kappa.astype(np.float64).tofile(f)
             np.ascontiguousarray(U, dtype=np.float64).tofile(f)
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+        if edge_blocks:
+            env["EMU_EDGE_BLOCKS"] = str(edge_blocks)
         r = subprocess.run([exe, fin, fout], capture_output=True, text=True, timeout=timeout,
                            env=env)
         if r.returncode != 0:
@@ -84,12 +88,14 @@ def main():
     ap.add_argument("--k1d", type=int, default=40)
     ap.add_argument("--N", type=int, default=4)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--edge-blocks", type=int, default=0)
     a = ap.parse_args()
     xyz, e2v = hex_pyramid_mesh(a.k1d, seed=a.seed)
     U = random_state(e2v.shape[0], a.N, seed=11)
     t = time.time()
-    out, local = run(xyz, e2v, a.N, U)
-    print(f"k1d={a.k1d} N={a.N} K={e2v.shape[0]}: finite={bool(np.isfinite(out).all())} "
+    out, local = run(xyz, e2v, a.N, U, edge_blocks=a.edge_blocks)
+    part = f"first and last {a.edge_blocks} workgroups" if a.edge_blocks else "every workgroup"
+    print(f"k1d={a.k1d} N={a.N} K={e2v.shape[0]} ({part}): finite={bool(np.isfinite(out).all())} "
           f"whole-hexahedron={local} {time.time() - t:.1f} s, no AddressSanitizer report")
 
 
