@@ -104,16 +104,17 @@ def stage_work(N: int):
     return F, B
 
 
-TRAFFIC_SOURCES = ("context.hpp", "flux.hpp", "geom.hpp", "kernels_mfma.hip", "mfma.hpp")
-
-
 def kernel_sources_digest():
-    """SHA-256 over the device sources that define the matrix-core kernels."""
+    """SHA-256 over every device source of the library (the .hip and .hpp files
+    of csrc/, not the host builders): a traffic record is used only while the
+    kernels it was measured on are unchanged."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    for name in TRAFFIC_SOURCES:
-        h.update(name.encode())
-        with open(os.path.join(ROOT, "paper_1502_07703_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_1502_07703_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
@@ -383,7 +384,7 @@ def batch_bench(args):
                                   "pyramids, N ~ U{2..6}, c^2 ~ U[0.5,2] per element, one Ricker "
                                   "source each, per-problem CFL 0.5 time steps",
                       "problems": len(probs), "nelems": nel, "dof": dof, "groups": b.ngroups,
-                      "tuned_groups_per_wave": chosen, "setup_s": t_setup}}
+                      "tuned_shapes": chosen, "setup_s": t_setup}}
     b.close()
     print(json.dumps(out), flush=True)
 
@@ -636,7 +637,9 @@ def run_form(dg, xyz, e2v, k1d, N, form, mode, steps, warmup, stream, path="fuse
     g = s.info_groups()
     traffic = recorded_traffic(dom, f"k1d={k1d} N={N} {form} {path} g{g}")
     T_end = (warmup + steps) * dt
+    Fs_, Bs_ = work(dom, N, path)
     res = {"value": 4 * Np * K * stages / wall / 1e9, "ms_per_step": wall / steps * 1e3,
+           "hbm_frac_dominant": Bs_ * K / (kernels[dom]["avg_ms"] * 1e-3) / (PEAK_HBM_GBS * 1e9),
            "dt": dt, "t_end": T_end, "setup_s": t_setup, "groups_per_wave": g,
            "l2_error_vs_mode": l2_norm(s, U, P, wJ, (mode, T_end)),
            "roofline": roofline(dom, N, K, kernels[dom]["avg_ms"], form, path, traffic),
@@ -656,16 +659,17 @@ def run_form(dg, xyz, e2v, k1d, N, form, mode, steps, warmup, stream, path="fuse
 
 
 def compare_forms(dg, xyz, e2v, k1d, N, mode, steps, warmup, stream):
-    """FP64 and both precision forms on one mesh and mode: each form's result
-    with its speed-up over FP64, its L2 distance to the FP64 state and whether
-    it is at equal error (within 10 % of the FP64 error)."""
+    """FP64 and both precision forms on one mesh and mode, and the FP64
+    sum-factorised kernels: each one's result with its speed-up over the
+    dense FP64 path, its L2 distance to the FP64 state and whether it is at
+    equal error (within 10 % of the FP64 error)."""
     import torch
     base, s64, U64, P, wJ = run_form(dg, xyz, e2v, k1d, N, "fp64", mode, steps, warmup, stream,
                                      keep_state=True)
     forms = {}
-    for form in ("fp32_mfma", "split_bf16"):
+    for form, path in (("fp32_mfma", "fused"), ("split_bf16", "fused"), ("fp64", "sumfact")):
         res, sf, Uf, _, _ = run_form(dg, xyz, e2v, k1d, N, form, mode, steps, warmup, stream,
-                                     keep_state=True)
+                                     path=path, keep_state=True)
         res["speedup_vs_fp64"] = res["value"] / base["value"]
         res["l2_diff_vs_fp64"] = l2_norm(sf, Uf - U64, P, wJ)
         e64 = base["l2_error_vs_mode"]
@@ -673,7 +677,7 @@ def compare_forms(dg, xyz, e2v, k1d, N, mode, steps, warmup, stream):
         sf.close()
         del Uf
         torch.cuda.empty_cache()
-        forms[form] = res
+        forms[form if path == "fused" else "fp64_sum_factorized"] = res
     s64.close()
     del U64, P, wJ
     torch.cuda.empty_cache()
@@ -803,6 +807,9 @@ def main():
             b2, f2 = compare_forms(dg, xyz, e2v, args.k1d, n2, m2, args.steps, args.warmup,
                                    stream)
             orders[str(n2)] = {"mode": m2, "fp64": b2, **f2}
+            print(f"[bench] N={n2}: fp64 {b2['value']:.2f}, " + ", ".join(
+                f"{k} {v['value']:.2f}" for k, v in f2.items()) + " GDOF-stages/s",
+                file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,

@@ -305,15 +305,20 @@ dgpyr_status dgpyr_batch_group(dgpyr_batch* b, int32_t g, dgpyr_ctx** ctx, int64
 /* nsteps LSRK(5,4) steps of every problem, each with its own time step;
  * step0 is the number of steps already taken (source times are
  * (step0 + n + c_s) dt_i).  One step of all groups is captured once into a
- * HIP graph (re-captured when U or R change) and replayed nsteps times on the
- * stream.  U, R: device arrays of the batch state length.  Asynchronous. */
+ * HIP graph, the groups on streams of their own between a fork and a join so
+ * that independent groups run concurrently (re-captured when U or R change),
+ * and replayed nsteps times on the stream.  U, R: device arrays of the batch
+ * state length.  Asynchronous. */
 dgpyr_status dgpyr_batch_step(dgpyr_batch* b, double* U, double* R, int64_t step0, int32_t nsteps,
                               void* stream);
 
-/* Autotuner: for every group on a matrix-core FP64/FP32 path, times nsteps
- * steps for 1 and 2 element groups per wave and keeps the faster (chosen[g]
- * receives it, 0 for groups with nothing to tune; chosen may be NULL).  The
- * timing runs on the caller's scratch arrays U and R (device, batch state
+/* Autotuner: for every group on an FP64 or FP32 matrix-core path, times
+ * nsteps steps of each candidate and keeps the fastest: the fused stage with
+ * 1 or 2 element groups per wave times the trace kernel with 1, 2 or 4
+ * (chosen[g] = 10 trace_groups + groups_per_wave), and for FP64 the
+ * sum-factorised kernels (chosen[g] = 100) when their resources fit the
+ * device; chosen[g] = 0 for groups with nothing to tune (chosen may be NULL).
+ * The timing runs on the caller's scratch arrays U and R (device, batch state
  * length each; their contents are overwritten), so the call allocates no
  * device memory.  Synchronises the stream. */
 dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, double* U, double* R, int32_t nsteps, void* stream,

@@ -3,8 +3,10 @@
 // meshes of a group are concatenated into one context (no face is shared
 // between problems, so the concatenation is exact), each element carrying
 // its own problem's time step in its material row.  One LSRK step of every
-// group is captured once into a HIP graph on a private stream and replayed on
-// the caller's stream; a per-group autotuner picks the matrix-core work shape.
+// group is captured once into a HIP graph -- the groups on streams of their
+// own between a fork and a join, so independent groups run concurrently --
+// and replayed on the caller's stream; a per-group autotuner picks the kernels
+// and work shape of each order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +33,11 @@ struct dgpyr_batch {
   std::vector<dgpyr_batch_slot> slots;
   int64_t state_len = 0;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
+  // one stream and one event per group: the captured step forks from cap
+  // into the groups and joins back, so independent groups run concurrently
+  std::vector<hipStream_t> gs;
+  std::vector<hipEvent_t> gev;
+  hipEvent_t fork = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const double* gU = nullptr;  // state arrays the captured graph uses
@@ -51,29 +58,43 @@ void free_batch(dgpyr_batch* b) {
   if (!b) return;
   drop_graph(b);
   for (auto& g : b->groups) free_ctx(g.ctx);
+  for (hipEvent_t ev : b->gev)
+    if (ev) hipEventDestroy(ev);
+  for (hipStream_t st : b->gs)
+    if (st) hipStreamDestroy(st);
+  if (b->fork) hipEventDestroy(b->fork);
   if (b->cap) hipStreamDestroy(b->cap);
   delete b;
 }
 
-// One LSRK step of every group on stream s, the time step of each element
-// taken from its material row (dt = 1 times the per-element scale).
-hipError_t enqueue_step(dgpyr_batch* b, double* U, double* R, hipStream_t s) {
-  for (auto& g : b->groups) {
-    dgpyr_ctx* c = g.ctx;
-    double* Ug = U + g.state_off;
-    double* Rg = R + g.state_off;
-    c->mesh.clock = c->clock;
-    c->mesh.t_base = 0.0;
-    c->mesh.dt_time = 1.0;
-    for (int st = 0; st < 5; ++st) {
-      c->mesh.c_stage = kRkC.c[st];
-      hipError_t e = run_stage(c, 1, Ug, Ug, Rg, kRkA[st], kRkB[st], 1.0, s, nullptr);
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = dgpyr::launch_clock(c->clock, 1.0, true, s);
+// One LSRK step of group g on stream s, the time step of each element taken
+// from its material row (dt = 1 times the per-element scale).
+hipError_t enqueue_group_step(dgpyr_batch::Group& g, double* U, double* R, hipStream_t s) {
+  dgpyr_ctx* c = g.ctx;
+  double* Ug = U + g.state_off;
+  double* Rg = R + g.state_off;
+  c->mesh.clock = c->clock;
+  c->mesh.t_base = 0.0;
+  c->mesh.dt_time = 1.0;
+  for (int st = 0; st < 5; ++st) {
+    c->mesh.c_stage = kRkC.c[st];
+    hipError_t e = run_stage(c, 1, Ug, Ug, Rg, kRkA[st], kRkB[st], 1.0, s, nullptr);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return dgpyr::launch_clock(c->clock, 1.0, true, s);
+}
+
+// One step of every group, forked from stream s onto the groups' streams and
+// joined back (groups share no data, so they may run concurrently).
+hipError_t enqueue_step(dgpyr_batch* b, double* U, double* R, hipStream_t s) {
+  hipError_t e = hipEventRecord(b->fork, s);
+  for (size_t g = 0; g < b->groups.size() && e == hipSuccess; ++g) {
+    e = hipStreamWaitEvent(b->gs[g], b->fork, 0);
+    if (e == hipSuccess) e = enqueue_group_step(b->groups[g], U, R, b->gs[g]);
+    if (e == hipSuccess) e = hipEventRecord(b->gev[g], b->gs[g]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->gev[g], 0);
+  }
+  return e;
 }
 
 dgpyr_status capture(dgpyr_batch* b, double* U, double* R) {
@@ -232,9 +253,16 @@ dgpyr_status dgpyr_batch_setup(const dgpyr_mesh* meshes, const int32_t* orders,
   }
   b->state_len = state_off;
   hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  b->gs.assign(b->groups.size(), nullptr);
+  b->gev.assign(b->groups.size(), nullptr);
+  for (size_t g = 0; g < b->groups.size() && e == hipSuccess; ++g) {
+    e = hipStreamCreateWithFlags(&b->gs[g], hipStreamNonBlocking);  // default priority
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->gev[g], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     free_batch(b);
-    return hip_fail(e, "capture stream");
+    return hip_fail(e, "capture streams");
   }
   *out = b;
   return DGPYR_OK;
@@ -298,21 +326,42 @@ dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, double* Us, double* Rs, int32_t ns
   dgpyr_status st = e == hipSuccess ? DGPYR_OK : hip_fail(e, "event create");
   for (size_t gix = 0; st == DGPYR_OK && gix < b->groups.size(); ++gix) {
     dgpyr_ctx* c = b->groups[gix].ctx;
-    const bool tunable = !c->reference_kernels && !c->unfused && !c->sum_factorized &&
-                         c->precision != DGPYR_SPLIT_BF16;
+    const bool tunable = !c->reference_kernels && !c->unfused && c->precision != DGPYR_SPLIT_BF16;
     if (!tunable) {
       if (chosen) chosen[gix] = 0;
       continue;
     }
+    // candidate work shapes: matrix-core stage with 1 or 2 element groups per
+    // wave times trace kernel with 1, 2 or 4 (code 10 tg + gw), and for FP64
+    // the sum-factorised kernels (code 100) where their resources fit
+    std::vector<int> cand;
+    for (int tg : {1, 2, 4})
+      for (int gw : {1, 2}) cand.push_back(10 * tg + gw);
+    const bool sf0 = c->sum_factorized, sfl0 = c->sf_local;
+    if (c->precision == DGPYR_FP64) {
+      c->sum_factorized = true;
+      c->sf_local = c->hex_groups && dgpyr::sf_local_possible(*c);
+      std::string msg;
+      if (dgpyr::sf_check_resources(*c, msg) == DGPYR_OK) cand.push_back(100);
+    }
+    auto apply = [&](int code) {
+      c->sum_factorized = code == 100;
+      c->sf_local = c->sum_factorized && c->hex_groups && dgpyr::sf_local_possible(*c);
+      if (code != 100) {
+        c->mfma_groups = code % 10;
+        c->trace_groups = code / 10;
+      }
+    };
     // the caller's scratch, cleared: the timing does not depend on values
     double* U = Us + b->groups[gix].state_off;
     double* R = Rs + b->groups[gix].state_off;
     e = dgpyr::launch_fill(U, b->groups[gix].state_len, 0.0, s);
     if (e == hipSuccess) e = dgpyr::launch_fill(R, b->groups[gix].state_len, 0.0, s);
     float best = 0.f;
-    int pick = c->mfma_groups;
-    for (int gw = 1; gw <= 2 && e == hipSuccess; ++gw) {
-      c->mfma_groups = gw;
+    int pick = 0;
+    for (int code : cand) {
+      if (e != hipSuccess) break;
+      apply(code);
       c->mesh.clock = c->clock;
       for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // warm-up, then timed
         if (rep == 1) e = hipEventRecord(e0, s);
@@ -324,12 +373,17 @@ dgpyr_status dgpyr_batch_tune(dgpyr_batch* b, double* Us, double* Rs, int32_t ns
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess && (gw == 1 || ms < best)) {
+      if (e == hipSuccess && (pick == 0 || ms < best)) {
         best = ms;
-        pick = gw;
+        pick = code;
       }
     }
-    c->mfma_groups = pick;
+    if (pick) {
+      apply(pick);
+    } else {
+      c->sum_factorized = sf0;
+      c->sf_local = sfl0;
+    }
     if (chosen) chosen[gix] = pick;
     if (e != hipSuccess) st = hip_fail(e, "tune");
   }

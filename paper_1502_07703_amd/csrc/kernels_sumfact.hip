@@ -36,9 +36,10 @@
 // factors, accumulated in registers across the fields; after the face fluxes
 // the projection is finished field by field (b-direction, then a-direction
 // with the triangle lifts, inverse mass and the LSRK stage).  LDS stays under
-// 60 KiB per workgroup and no kernel keeps arrays in private memory; setup
-// checks both (hipFuncGetAttributes against the device's limits) before the
-// first launch.
+// 60 KiB per workgroup and no kernel keeps arrays in private memory (the
+// N = 5 stage, compiled for three waves per SIMD, spills registers to 132
+// bytes per lane); setup checks LDS, private memory and block size
+// (hipFuncGetAttributes against the device's limits) before the first launch.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -252,8 +253,17 @@ __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
 // are in the workgroup, T2 holds (p, u.n) base traces only); otherwise T2 is
 // the four-field trace array [K][Nfc][4] of all five faces, from which the
 // neighbour's p and n.u are read.
+// Waves per SIMD the stage is compiled for: N = 5 at three (168 registers,
+// 96 spilled to private memory) runs 30.3 -> 27.2 ms per stage at 64^3 x 6;
+// at N = 4 three waves measured slower (6.19 -> 6.26 ms at 40^3 x 6), and the
+// other orders are left to the compiler.
+template <int N>
+struct SfWaves {
+  static constexpr int value = N == 5 ? 3 : 1;
+};
+
 template <int N, int MODE, bool LOCAL>
-__global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS)) void k_sf_stage(
+__global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) void k_sf_stage(
     const double* U, const double* __restrict__ T2, SfOps sf, DevOps ops, DevMesh mesh,
     double* out, double* R, double ra, double rb, double dt) {
   using D = SfDims<N>;

@@ -136,11 +136,13 @@ def test_batch_tune_keeps_results():
         R = b.empty_state().zero_()
         b.step(U, R, 2)
         chosen = b.tune(2)
-        log(f"[batch] tuned groups per wave {chosen}")
-        assert all(c in (0, 1, 2) for c in chosen)
+        log(f"[batch] tuned shapes {chosen}")
+        assert all(c in (0, 100) or (c % 10 in (1, 2) and c // 10 in (1, 2, 4)) for c in chosen)
         U2 = U0.clone()
         R2 = b.empty_state().zero_()
         b.step(U2, R2, 2)
         torch.cuda.synchronize()
         scale = U.abs().max().item()
-        assert (U2 - U).abs().max().item() <= 1e-13 * scale
+        # another work shape (or the sum-factorised kernels) changes only the
+        # rounding order
+        assert (U2 - U).abs().max().item() <= 1e-12 * scale
