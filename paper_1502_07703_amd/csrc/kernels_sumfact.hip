@@ -37,9 +37,10 @@
 // the projection is finished field by field (b-direction, then a-direction
 // with the triangle lifts, inverse mass and the LSRK stage).  LDS stays under
 // 60 KiB per workgroup and no kernel keeps arrays in private memory (the
-// N = 5 stage, compiled for three waves per SIMD, spills registers to 132
-// bytes per lane); setup checks LDS, private memory and block size
-// (hipFuncGetAttributes against the device's limits) before the first launch.
+// N = 5 stage, compiled for three waves per SIMD, spills the velocity rows'
+// projections across the first projection pass, 148 bytes per lane); setup
+// checks LDS, private memory and block size (hipFuncGetAttributes against the
+// device's limits) before the first launch.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -111,11 +112,28 @@ struct SfShape {
 __device__ __forceinline__ int kofs(int k) { return k * (k + 1) * (2 * k + 1) / 6; }
 __device__ __forceinline__ int kjofs(int k) { return k * (k + 1) / 2; }
 
-// (k, j) of a pair index kj = k (k+1)/2 + j.
+// (k, j) of a pair index kj = k (k+1)/2 + j, 0 <= kj < (N+1)(N+2)/2, by N
+// comparisons (no lane-divergent loop).
+template <int N>
 __device__ __forceinline__ void kj_split(int kj, int& k, int& j) {
   k = 0;
-  while (kjofs(k + 1) <= kj) ++k;
+#pragma unroll
+  for (int t = 1; t <= N; ++t) k += kj >= kjofs(t) ? 1 : 0;
   j = kj - kjofs(k);
+}
+
+// (k, j, i) of a coefficient index n = kofs(k) + j (k+1) + i, 0 <= n < Np,
+// by comparisons only.
+template <int N>
+__device__ __forceinline__ void kji_split(int n, int& k, int& j, int& i) {
+  k = 0;
+#pragma unroll
+  for (int t = 1; t <= N; ++t) k += n >= kofs(t) ? 1 : 0;
+  const int rem = n - kofs(k);
+  j = 0;
+#pragma unroll
+  for (int t = 1; t <= N; ++t) j += rem >= t * (k + 1) ? 1 : 0;
+  i = rem - j * (k + 1);
 }
 
 // Penalty flux from the jumps at one face point (Section 4.3):
@@ -254,9 +272,9 @@ __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
 // the four-field trace array [K][Nfc][4] of all five faces, from which the
 // neighbour's p and n.u are read.
 // Waves per SIMD the stage is compiled for: N = 5 at three (168 registers,
-// 96 spilled to private memory) runs 30.3 -> 27.2 ms per stage at 64^3 x 6;
-// at N = 4 three waves measured slower (6.19 -> 6.26 ms at 40^3 x 6), and the
-// other orders are left to the compiler.
+// some spilled to private memory) ran 30.3 -> 27.2 ms per stage at 64^3 x 6
+// when it was introduced; at N = 4 three waves measured slower (20.7 ->
+// 22.5 ms at 64^3 x 6), and the other orders are left to the compiler.
 template <int N>
 struct SfWaves {
   static constexpr int value = N == 5 ? 3 : 1;
@@ -338,20 +356,37 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
 #pragma unroll
   for (int r = 0; r < n1; ++r) qp[r] = 0.0;
 
-  // ---- volume term and own traces, one field at a time
+  // ---- volume term and own traces, one field at a time: the velocities
+  // first (they only add to the pressure row's projection), the pressure
+  // last, so that the velocity rows' projections are live in registers only
+  // from there on
+  // The next field's coefficients are loaded into registers while the current
+  // field's a-direction runs and stored into LDS once its readers are past the
+  // barrier, so a field costs two barriers and its load latency is hidden.
+  constexpr int LD = (E * Np + NT - 1) / NT;  // coefficients each thread stages
+  for (int x = tid; x < E * Np; x += NT) {
+    const int l = x / Np, n = x % Np;
+    sUD[l][n] = l < ne ? U[((e0 + l) * 4 + 1) * Np + n] : 0.0;
+  }
+  __syncthreads();
 #pragma unroll
-  for (int fld = 0; fld < 4; ++fld) {
-    for (int x = tid; x < E * Np; x += NT) {
-      const int l = x / Np, n = x % Np;
-      sUD[l][n] = l < ne ? U[((e0 + l) * 4 + fld) * Np + n] : 0.0;
+  for (int it = 0; it < 4; ++it) {
+    const int fld = (it + 1) & 3;
+    double nxt[LD];
+    if (it < 3) {
+      const int nfld = (it + 2) & 3;
+#pragma unroll
+      for (int q = 0; q < LD; ++q) {
+        const int x = tid + q * NT, l = x / Np, n = x % Np;
+        nxt[q] = (x < E * Np && l < ne) ? U[((e0 + l) * 4 + nfld) * Np + n] : 0.0;
+      }
     }
-    __syncthreads();
     // a-direction: A[kj][p] = sum_i l_i(a_p) u_ijk, A'[kj][p] with l'_i(a_p)
     for (int x = tid; x < ne * KJ * n1; x += NT) {
       const int l = x / (KJ * n1), rem = x % (KJ * n1);
       const int kj = rem / n1, pp = rem % n1;
       int k, j;
-      kj_split(kj, k, j);
+      kj_split<N>(kj, k, j);
       const double* u = sUD[l] + kofs(k) + j * (k + 1);
       const double* La = sLa + (k * n1 + pp) * n1;
       const double* Da = sDa + (k * n1 + pp) * n1;
@@ -401,6 +436,13 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       }
     }
     __syncthreads();
+    if (it < 3) {
+#pragma unroll
+      for (int q = 0; q < LD; ++q) {
+        const int x = tid + q * NT;
+        if (x < E * Np) sUD[x / Np][x % Np] = nxt[q];
+      }
+    }
     // b- and c-directions, metric and projection along c, per column
     if (col) {
       double s0[n1], sa[n1], sb[n1];
@@ -569,7 +611,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       const int l = x / (KJ * n1), rem = x % (KJ * n1);
       const int kj = rem / n1, pp = rem % n1;
       int k, j;
-      kj_split(kj, k, j);
+      kj_split<N>(kj, k, j);
       const double* B = sAB[l] + k * n2 + pp;
       double acc = 0.0;
 #pragma unroll
@@ -579,9 +621,8 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
     __syncthreads();
     for (int x = tid; x < ne * Np; x += NT) {
       const int l = x / Np, n = x % Np;
-      int k = 0;
-      while (kofs(k + 1) <= n) ++k;
-      const int rem = n - kofs(k), j = rem / (k + 1), i = rem % (k + 1);
+      int k, j, i;
+      kji_split<N>(n, k, j, i);
       const double* La_k = sLa + k * n2;  // [p][i]
       const double* Dk = sUD[l] + (kjofs(k) + j) * n1;
       const double* cc = D::kSeparateC ? (const double*)sCC[l] : (const double*)sTT[l];
