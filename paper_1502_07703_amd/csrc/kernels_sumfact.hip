@@ -31,9 +31,11 @@
 //
 // Work shape.  A workgroup owns E elements and one thread per (element, a, b)
 // column.  The four fields are processed one at a time through LDS: the
-// a-direction contraction (all threads), then per column the b- and c-
-// direction contractions, the FP64 metric and the projection onto the c
-// factors, accumulated in registers across the fields; after the face fluxes
+// a-direction contraction at the a-points and at a = -1, +1 (all threads),
+// then per column the b- and c-direction contractions, the FP64 metric and
+// the projection onto the c factors, accumulated in registers across the
+// fields, and beside them the triangle traces as b- and c-contractions of the
+// a-direction results; after the face fluxes
 // the projection is finished field by field (b-direction, then a-direction
 // with the triangle lifts, inverse mass and the LSRK stage).  LDS stays under
 // 60 KiB per workgroup and no kernel keeps arrays in private memory (the
@@ -73,7 +75,9 @@ struct SfDims {
   static constexpr int Nfc = 5 * n2;
   // per-element LDS regions (doubles):
   static constexpr int UD = KJ * n1;      // U of one field, then D [kj][p]
-  static constexpr int AB = 2 * KJ * n1;  // A, A' [2][kj][p], then B [k][m][p] (n3 <= AB)
+  // A, A' [2][kj][p] and the a = -1, +1 values Ae [kj][2]; then B [k][m][p]
+  // (n3 <= AB)
+  static constexpr int AB = 2 * KJ * n1 + 2 * KJ;
   static constexpr int TT = 8 * n2;       // triangle traces [face][p, u.n][point]
   // folded triangle fluxes [face][2][k][p] overwrite the traces when every
   // thread owns at most one (element, face, a) item (4 n1 <= n2), else they
@@ -400,39 +404,15 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       }
       sAB[l][kj * n1 + pp] = a;
       sAB[l][KJ * n1 + kj * n1 + pp] = ad;
-    }
-    // triangle traces of this field: item (element, face, edge point)
-    for (int x = tid; x < ne * 4 * n1; x += NT) {
-      const int l = x / (4 * n1), rem = x % (4 * n1);
-      const int ft = rem / n1, pp = rem % n1, f = ft + 1;
-      const double* Le_s = sLe + ((f == 2 || f == 4) ? 1 : 0) * n1;
-      double val[n1];
+      // Ae[kj][s] = sum_i l_i(-1 or +1) u_ijk, by the items p = 0 and 1 (p = 0
+      // takes both when N = 0)
+      for (int sd = pp; sd < 2; sd += n1) {
+        const double* Le = sLe + (k * 2 + sd) * n1;
+        double ae = 0.0;
 #pragma unroll
-      for (int mm = 0; mm < n1; ++mm) val[mm] = 0.0;
-#pragma unroll
-      for (int k = 0; k <= N; ++k) {
-        const double* uk = sUD[l] + kofs(k);
-        const double* La_p = sLa + (k * n1 + pp) * n1;
-        const double* Le_k = Le_s + k * 2 * n1;
-        double Y = 0.0;
-#pragma unroll 1
-        for (int j = 0; j <= k; ++j) {  // rows one at a time (register pressure)
-          double acc = 0.0;
-#pragma unroll
-          for (int i = 0; i <= k; ++i) acc += (f <= 2 ? Le_k[i] : La_p[i]) * uk[j * (k + 1) + i];
-          Y += (f <= 2 ? La_p[j] : Le_k[j]) * acc;
-        }
-#pragma unroll
-        for (int mm = 0; mm < n1; ++mm) val[mm] += sf.Gf[mm * n1 + k] * Y;
-      }
-      double* tt = sTT[l] + ft * 2 * n2;
-      const double nd = fld == 0 ? 0.0 : sN[l][ft][fld - 1];
-#pragma unroll
-      for (int mm = 0; mm < n1; ++mm) {
-        const int pt = pp + n1 * mm;
-        if (fld == 0) tt[pt] = val[mm];
-        else if (fld == 1) tt[n2 + pt] = nd * val[mm];
-        else tt[n2 + pt] += nd * val[mm];
+        for (int i = 0; i < n1; ++i)
+          if (i <= k) ae += Le[i] * u[i];
+        sAB[l][2 * KJ * n1 + kj * 2 + sd] = ae;
       }
     }
     __syncthreads();
@@ -487,6 +467,41 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
           const int d = fld - 1;
           qp[r] += adj[d] * dr + adj[3 + d] * ds + adj[6 + d] * dtt;
         }
+      }
+    }
+    // triangle traces of this field from the a-direction results, item
+    // (element, face, edge point p), at the face points (p, c_m):
+    //   a = -1, +1 (faces 1, 2): sum_k g_k(c_m) sum_j l_j(b_p) Ae[kj][s],
+    //   b = -1, +1 (faces 3, 4): sum_k g_k(c_m) sum_j l_j(-1 or +1) A[kj][p]
+    for (int x = tid; x < ne * 4 * n1; x += NT) {
+      const int l = x / (4 * n1), rem = x % (4 * n1);
+      const int ft = rem / n1, pp = rem % n1, f = ft + 1;
+      const int sd = (f == 2 || f == 4) ? 1 : 0;
+      const bool afc = f <= 2;
+      double val[n1];
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) val[mm] = 0.0;
+#pragma unroll
+      for (int k = 0; k <= N; ++k) {
+        // weights and values of row j: (l_j(b_p), Ae[kj][s]) or (l_j(+-1), A[kj][p])
+        const double* w = afc ? sLa + (k * n1 + pp) * n1 : sLe + (k * 2 + sd) * n1;
+        const double* X = afc ? sAB[l] + 2 * KJ * n1 + kjofs(k) * 2 + sd
+                              : sAB[l] + kjofs(k) * n1 + pp;
+        const int xs = afc ? 2 : n1;
+        double Y = 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) Y += w[j] * X[j * xs];
+#pragma unroll
+        for (int mm = 0; mm < n1; ++mm) val[mm] += sf.Gf[mm * n1 + k] * Y;
+      }
+      double* tt = sTT[l] + ft * 2 * n2;
+      const double nd = fld == 0 ? 0.0 : sN[l][ft][fld - 1];
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) {
+        const int pt = pp + n1 * mm;
+        if (fld == 0) tt[pt] = val[mm];
+        else if (fld == 1) tt[n2 + pt] = nd * val[mm];
+        else tt[n2 + pt] += nd * val[mm];
       }
     }
     __syncthreads();
