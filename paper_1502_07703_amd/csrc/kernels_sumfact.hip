@@ -39,8 +39,8 @@
 // the projection is finished field by field (b-direction, then a-direction
 // with the triangle lifts, inverse mass and the LSRK stage).  LDS stays under
 // 60 KiB per workgroup and no kernel keeps arrays in private memory (the
-// N = 5 stage, compiled for three waves per SIMD, spills the velocity rows'
-// projections across the first projection pass, 148 bytes per lane); setup
+// N = 5 stage, compiled for three waves per SIMD, spills a few registers, 52
+// bytes per lane); setup
 // checks LDS, private memory and block size (hipFuncGetAttributes against the
 // device's limits) before the first launch.
 #include <hip/hip_runtime.h>
@@ -84,7 +84,7 @@ struct SfDims {
   // need a region of their own
   static constexpr bool kSeparateC = 4 * n1 > n2;
   static constexpr int CC = kSeparateC ? 8 * n2 : 0;
-  static constexpr int kTables = 16 + 16 + 5 + 10;  // vertices, normals, rho c, ints
+  static constexpr int kTables = 16 + 16 + 5 + 4 + 10;  // vertices, normals, rho c, material, ints
   static constexpr int PER_ELEM = kTables + UD + AB + TT + CC;
   static constexpr int PERM_BYTES = 10 * n2 * 4;
   // one-dimensional factors read with lane-dependent indices, staged in LDS
@@ -295,6 +295,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   __shared__ double sX[E][16];
   __shared__ double sN[E][4][4];   // triangle faces 1..4: unit normal, sJ
   __shared__ double sZ[E][5];      // rho c across each face (own on the boundary)
+  __shared__ double sM[E][4];      // kappa, 1/rho, rho c, time-step scale
   __shared__ int sNb[E][5][4];     // neighbour, its index in the workgroup or -1, its face, permutation row
   __shared__ double sUD[E][D::UD];
   __shared__ double sAB[E][D::AB];
@@ -312,6 +313,10 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   for (int x = tid; x < E * 16; x += NT) {
     const int le = x / 16;
     sX[le][x % 16] = le < ne ? mesh.verts[(e0 + le) * 16 + x % 16] : 0.0;
+  }
+  for (int x = tid; x < E * 4; x += NT) {
+    const int le = x / 4;
+    sM[le][x % 4] = le < ne ? mesh.mat[(e0 + le) * 4 + x % 4] : 0.0;
   }
   for (int x = tid; x < 10 * n2; x += NT) sPerm[x] = ops.perm[x];
   __syncthreads();
@@ -394,13 +399,16 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       const double* u = sUD[l] + kofs(k) + j * (k + 1);
       const double* La = sLa + (k * n1 + pp) * n1;
       const double* Da = sDa + (k * n1 + pp) * n1;
+      // all n1 terms without branches: the factor tables hold zeros beyond
+      // i = k, and the row's neighbours in LDS (read in bounds) are masked
+      double uu[n1];
+#pragma unroll
+      for (int i = 0; i < n1; ++i) uu[i] = i <= k ? u[i] : 0.0;
       double a = 0.0, ad = 0.0;
 #pragma unroll
       for (int i = 0; i < n1; ++i) {
-        if (i <= k) {
-          a += La[i] * u[i];
-          ad += Da[i] * u[i];
-        }
+        a += La[i] * uu[i];
+        ad += Da[i] * uu[i];
       }
       sAB[l][kj * n1 + pp] = a;
       sAB[l][KJ * n1 + kj * n1 + pp] = ad;
@@ -410,8 +418,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
         const double* Le = sLe + (k * 2 + sd) * n1;
         double ae = 0.0;
 #pragma unroll
-        for (int i = 0; i < n1; ++i)
-          if (i <= k) ae += Le[i] * u[i];
+        for (int i = 0; i < n1; ++i) ae += Le[i] * uu[i];
         sAB[l][2 * KJ * n1 + kj * 2 + sd] = ae;
       }
     }
@@ -613,9 +620,32 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   }
 
   // ---- projection, one field at a time: b-direction, then a-direction with
-  // the triangle lifts, inverse mass, material and the RK stage
+  // the triangle lifts, inverse mass, material and the RK stage.  The inverse
+  // mass diagonal of this thread's coefficients is evaluated once for the
+  // four fields.
+  double minv[LD];
+#pragma unroll
+  for (int q = 0; q < LD; ++q) {
+    const int x = tid + q * NT, l = x / Np, n = x % Np;
+    minv[q] = x < ne * Np ? 1.0 / (pyr_jac(sX[l], ops.na[n], ops.nb[n]) * ops.wwc[n]) : 0.0;
+  }
 #pragma unroll
   for (int fld = 0; fld < 4; ++fld) {
+    // in RK mode this field's state and residual are loaded here, ahead of
+    // the b-direction pass, and used by the update at its end
+    double uo[LD], ro[LD];
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int q = 0; q < LD; ++q) {
+        const int x = tid + q * NT;
+        uo[q] = ro[q] = 0.0;
+        if (x < ne * Np) {
+          const int64_t idx = ((e0 + x / Np) * 4 + fld) * Np + x % Np;
+          uo[q] = out[idx];
+          if (ra != 0.0) ro[q] = R[idx];
+        }
+      }
+    }
     if (col) {
 #pragma unroll
       for (int k = 0; k < n1; ++k) sAB[le][k * n2 + m * n1 + p] = bacc[fld][k];
@@ -634,7 +664,10 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       sUD[l][kj * n1 + pp] = acc;
     }
     __syncthreads();
-    for (int x = tid; x < ne * Np; x += NT) {
+#pragma unroll
+    for (int q = 0; q < LD; ++q) {
+      const int x = tid + q * NT;
+      if (x >= ne * Np) continue;
       const int l = x / Np, n = x % Np;
       int k, j, i;
       kji_split<N>(n, k, j, i);
@@ -663,10 +696,15 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       v += s1 * Le_k[i] * t1 + s2 * Le_k[n1 + i] * t2 + s3 * Le_k[j] * t3 + s4 * Le_k[n1 + j] * t4;
       const int64_t el = e0 + l;
       if (fld == 0) v -= source_term<Np>(mesh, el, n);
-      const double minv = 1.0 / (pyr_jac(sX[l], ops.na[n], ops.nb[n]) * ops.wwc[n]);
-      const double mat = mesh.mat[el * 4 + (fld == 0 ? 0 : 1)];
-      finish_coeff<MODE>(v, minv, mat, out, R, (el * 4 + fld) * Np + n, ra, rb,
-                         dt * mesh.mat[el * 4 + 3]);
+      const int64_t idx = (el * 4 + fld) * Np + n;
+      const double rhs = -sM[l][fld == 0 ? 0 : 1] * minv[q] * v;
+      if constexpr (MODE == 0) {
+        out[idx] = rhs;
+      } else {  // R <- ra R + dt rhs, U <- U + rb R (finish_coeff with the loads above)
+        const double rn = ra * ro[q] + dt * sM[l][3] * rhs;
+        R[idx] = rn;
+        out[idx] = uo[q] + rb * rn;
+      }
     }
     __syncthreads();
   }
