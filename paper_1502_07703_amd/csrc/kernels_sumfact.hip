@@ -438,8 +438,8 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
         const double* La_m = sLa + (k * n1 + m) * n1;
         const double* Da_m = sDa + (k * n1 + m) * n1;
         double x0 = 0.0, xa = 0.0, xb = 0.0;
-#pragma unroll 1
-        for (int j = 0; j <= k; ++j) {  // one row at a time (register pressure)
+#pragma unroll
+        for (int j = 0; j <= k; ++j) {
           const double A = sAB[le][(kjofs(k) + j) * n1 + p];
           const double Ad = sAB[le][KJ * n1 + (kjofs(k) + j) * n1 + p];
           x0 += La_m[j] * A;
