@@ -496,7 +496,7 @@ def adjoint_bench(args):
     from synth import hex_pyramid_mesh
     xyz, e2v = hex_pyramid_mesh(args.adjoint_k1d, seed=5)
     K = e2v.shape[0]
-    N = args.N
+    N = args.N if args.N is not None else 4  # the adjoint configuration's order
     rng = np.random.default_rng(5000)
     cent = xyz[e2v].mean(axis=1)
     F = np.zeros(K)
@@ -710,7 +710,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--k1d", type=int, default=64)
-    ap.add_argument("--N", type=int, default=5)
+    ap.add_argument("--N", type=int, default=None,
+                    help="order (default 5 for the headline line, 4 for --adjoint)")
     ap.add_argument("--extra-N", default="6,7",
                     help="further orders run after the headline one (comma list, '' for none)")
     ap.add_argument("--mode", type=int, default=0,
@@ -772,7 +773,7 @@ def main():
 
     from synth import hex_pyramid_mesh
     headline = not (args.study or args.batch or args.adjoint or args.advection)
-    N = args.N
+    N = args.N if args.N is not None else 5
     xyz = e2v = None
     cpu = cpu1 = None
     if headline:
