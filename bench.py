@@ -94,9 +94,9 @@ def sf_work(name: str, N: int, local: bool = True):
 
 def work(name: str, N: int, path: str = "fused"):
     """Per-element work of one launch of kernel ``name`` on kernel path ``path``."""
-    # the sum-factorised stage owns whole hexahedra up to N = 6 (the bench
+    # the sum-factorised stage owns whole hexahedra up to N = 5 (the bench
     # meshes come in hexahedra), else it reads all-face traces
-    return sf_work(name, N, local=N <= 6) if path == "sumfact" else kernel_work(name, N)
+    return sf_work(name, N, local=N <= 5) if path == "sumfact" else kernel_work(name, N)
 
 
 def stage_work(N: int):

@@ -24,8 +24,8 @@
 // hexahedron pair their four triangle faces among themselves; when the mesh
 // comes in such groups a workgroup owns whole hexahedra and exchanges the
 // triangle traces in LDS, and only the quadrilateral base traces go through
-// HBM (written by k_sf_trace).  Otherwise (general meshes, and N = 7, 8 where
-// six elements do not fit a workgroup) the traces of all five faces come from
+// HBM (written by k_sf_trace).  Otherwise (general meshes, and N >= 6 where
+// six elements do not fit four waves) the traces of all five faces come from
 // the FP64 matrix-core trace kernel in the [K][Nfc][4] layout and the stage
 // reads its neighbours' from HBM.
 //
@@ -92,20 +92,23 @@ struct SfDims {
   // [k][s][i]
   static constexpr int TAB = 2 * n3 + 2 * n2;
   static constexpr int bytes(int E) { return E * PER_ELEM * 8 + PERM_BYTES + TAB * 8; }
-  // elements per workgroup when hexahedra (6 elements) are kept whole, 0 if
-  // not even one fits: as many hexahedra as fit 256 columns (one hexahedron
-  // up to 512), so that several workgroups share a CU -- at 64^3 x 6 one
-  // hexahedron per workgroup instead of two halves the stage at N = 3 and 4
-  // (8.55 -> 4.28 ms, 16.4 -> 9.3 ms)
+  // Elements per workgroup: at most 256 columns (four waves), so that
+  // several workgroups share a CU at the two or three waves per SIMD these
+  // kernels' registers allow.  Measured at 64^3 x 6: one hexahedron per
+  // workgroup instead of two halves the stage at N = 3 and 4 (8.55 -> 4.28
+  // ms, 16.4 -> 9.3 ms); at N = 6, where one hexahedron needs five waves and
+  // only one such workgroup fits a CU, the general variant with 5 elements
+  // per workgroup is faster despite its all-face traces (stage 46.9 -> 35.0
+  // ms, trace 7.3 -> 9.3 ms).
+  // Whole hexahedra (6 elements each), 0 if not even one fits:
   static constexpr int hex_elems() {
     int best = 0;
-    for (int H = 1; 6 * H * n2 <= (H == 1 ? 512 : 256) && bytes(6 * H) <= kLdsBudget; ++H)
-      best = 6 * H;
+    for (int H = 1; 6 * H * n2 <= 256 && bytes(6 * H) <= kLdsBudget; ++H) best = 6 * H;
     return best;
   }
   static constexpr int free_elems() {
     int best = 1;
-    for (int E = 1; E * n2 <= 512 && bytes(E) <= kLdsBudget; ++E) best = E;
+    for (int E = 1; E * n2 <= 256 && bytes(E) <= kLdsBudget; ++E) best = E;
     return best;
   }
 };
