@@ -210,7 +210,7 @@ hipError_t launch_volume_mfma(const dgpyr_ctx& c, const double* U, double* vol, 
 hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t s);
 // Sum-factorised FP64 kernels (kernels_sumfact.hip).  On whole hexahedra
 // (sf_local) the traces are (p, u.n) pairs of the base faces, [K][(N+1)^2][2];
-// otherwise the four-field traces of all faces [K][Nfc][4].
+// otherwise of all five faces, [K][Nfc][2].
 hipError_t launch_sf_trace(const dgpyr_ctx& c, const double* U, double* T2, hipStream_t s);
 hipError_t launch_sf_stage(const dgpyr_ctx& c, int mode, const double* U, const double* T2,
                            double* out, double* R, double ra, double rb, double dt, hipStream_t s);

@@ -25,9 +25,9 @@
 // comes in such groups a workgroup owns whole hexahedra and exchanges the
 // triangle traces in LDS, and only the quadrilateral base traces go through
 // HBM (written by k_sf_trace).  Otherwise (general meshes, and N >= 6 where
-// six elements do not fit four waves) the traces of all five faces come from
-// the FP64 matrix-core trace kernel in the [K][Nfc][4] layout and the stage
-// reads its neighbours' from HBM.
+// six elements do not fit four waves) k_sf_trace_all writes the (p, u.n)
+// pairs of all five faces, [K][Nfc][2], and the stage reads its neighbours'
+// from HBM.
 //
 // Work shape.  A workgroup owns E elements and one thread per (element, a, b)
 // column.  The four fields are processed one at a time through LDS: the
@@ -278,10 +278,140 @@ __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
 }
 
 // ---------------------------------------------------------------------------
+// Traces (p, u.n) of all five faces, T2[K][5 (N+1)^2][2] in the face order of
+// the face points (base, then a = -1, +1, b = -1, +1), for the general variant
+// of the stage.  The workgroup's state is staged in LDS; field by field the
+// a-direction contractions at the a-points and at a = -1, +1, then one item
+// per base point (b- and c-directions) and one per triangle edge point p (the
+// line of face points (p, c_m), as in the stage).  The pressure is written at
+// once, the normal velocity after the last field.  At 64^3 x 6 it takes
+// 10.9 ms at N = 6 and 12.6 ms at N = 7, against 9.3 and 16.9 ms for the
+// four-field matrix-core trace it replaces (the stage then reads half the
+// trace bytes); all four fields' a-direction results at once, behind a single
+// barrier, measured slower (12.9 and 15.4 ms) from the registers the fused
+// item loops need.
+template <int N>
+struct TraceAllShape {
+  using D = SfDims<N>;
+  static constexpr int P = D::n2 + 4 * D::n1;  // items per element
+  static constexpr int E = 256 / P < 1 ? 1 : 256 / P;
+  static constexpr int THREADS = round64(E * P);
+};
+
+template <int N>
+__global__ __launch_bounds__((TraceAllShape<N>::THREADS)) void k_sf_trace_all(
+    const double* __restrict__ U, double* __restrict__ T2, SfOps sf, DevOps ops,
+    const double* __restrict__ verts, int64_t K) {
+  using D = SfDims<N>;
+  using TS = TraceAllShape<N>;
+  constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, KJ = D::KJ, E = TS::E, NT = TS::THREADS;
+  constexpr int P = TS::P;
+  __shared__ double sU[E][4 * Np];
+  __shared__ double sA[E][KJ * n1 + 2 * KJ];  // A [kj][p], Ae [kj][2]
+  __shared__ double sX[E][16];
+  __shared__ double sN[E][4][4];  // triangle faces: unit normal, sJ
+  __shared__ double sLa[D::n3], sLe[2 * n2];
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = (int)(K - e0 < E ? K - e0 : E);
+  for (int x = tid; x < ne * 4 * Np; x += NT) sU[x / (4 * Np)][x % (4 * Np)] = U[e0 * 4 * Np + x];
+  for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
+  for (int x = tid; x < D::n3; x += NT) sLa[x] = sf.La[x];
+  for (int x = tid; x < 2 * n2; x += NT) sLe[x] = sf.Le[x];
+  __syncthreads();
+  for (int x = tid; x < ne * 4; x += NT) {
+    const int l = x / 4, f = x % 4 + 1;
+    face_normal_unit(sX[l], f, ops.fa[f * n2], ops.fb[f * n2], sN[l][f - 1]);
+  }
+  // this thread's item: element l, base point q < n2 or triangle edge point
+  const bool item = tid < ne * P;
+  const int l = item ? tid / P : 0, q = tid % P;
+  const bool base = q < n2;
+  const int ft = base ? 0 : (q - n2) / n1, pp = base ? q % n1 : (q - n2) % n1;
+  const int m = base ? q / n1 : 0;
+  double nb[4] = {0.0, 0.0, 0.0, 0.0};
+  if (item && base) face_normal_unit(sX[l], 0, ops.xg[pp], ops.xg[m], nb);
+  double* row = T2 + (e0 + l) * 5 * n2 * 2;  // this element's pairs
+  double un[n1];                              // u.n along this thread's line
+#pragma unroll
+  for (int mm = 0; mm < n1; ++mm) un[mm] = 0.0;
+#pragma unroll
+  for (int fld = 0; fld < 4; ++fld) {
+    for (int x = tid; x < ne * KJ * n1; x += NT) {
+      const int el = x / (KJ * n1), rem = x % (KJ * n1);
+      const int kj = rem / n1, p = rem % n1;
+      int k, j;
+      kj_split<N>(kj, k, j);
+      const double* u = sU[el] + fld * Np + kofs(k) + j * (k + 1);
+      double uu[n1];
+#pragma unroll
+      for (int i = 0; i < n1; ++i) uu[i] = i <= k ? u[i] : 0.0;
+      const double* La = sLa + (k * n1 + p) * n1;
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < n1; ++i) a += La[i] * uu[i];
+      sA[el][kj * n1 + p] = a;
+      for (int sd = p; sd < 2; sd += n1) {
+        const double* Le = sLe + (k * 2 + sd) * n1;
+        double ae = 0.0;
+#pragma unroll
+        for (int i = 0; i < n1; ++i) ae += Le[i] * uu[i];
+        sA[el][KJ * n1 + kj * 2 + sd] = ae;
+      }
+    }
+    __syncthreads();
+    if (item && base) {
+      // u(a_p, b_m, -1) = sum_k g_k(-1) sum_j l_j(b_m) A[kj][p]
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k <= N; ++k) {
+        const double* Lm = sLa + (k * n1 + m) * n1;
+        double Y = 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) Y += Lm[j] * sA[l][(kjofs(k) + j) * n1 + pp];
+        v += sf.Gb[k] * Y;
+      }
+      if (fld == 0) row[q * 2] = v;
+      else un[0] += nb[fld - 1] * v;
+    } else if (item) {
+      // faces 1, 2 (a = -1, +1): sum_k g_k(c_m) sum_j l_j(b_p) Ae[kj][s];
+      // faces 3, 4 (b = -1, +1): sum_k g_k(c_m) sum_j l_j(-1 or +1) A[kj][p]
+      const int f = ft + 1, sd = (f == 2 || f == 4) ? 1 : 0;
+      const bool afc = f <= 2;
+      double val[n1];
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) val[mm] = 0.0;
+#pragma unroll
+      for (int k = 0; k <= N; ++k) {
+        const double* w = afc ? sLa + (k * n1 + pp) * n1 : sLe + (k * 2 + sd) * n1;
+        const double* X = afc ? sA[l] + KJ * n1 + kjofs(k) * 2 + sd : sA[l] + kjofs(k) * n1 + pp;
+        const int xs = afc ? 2 : n1;
+        double Y = 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) Y += w[j] * X[j * xs];
+#pragma unroll
+        for (int mm = 0; mm < n1; ++mm) val[mm] += sf.Gf[mm * n1 + k] * Y;
+      }
+#pragma unroll
+      for (int mm = 0; mm < n1; ++mm) {
+        if (fld == 0) row[(f * n2 + pp + n1 * mm) * 2] = val[mm];
+        else un[mm] += sN[l][ft][fld - 1] * val[mm];
+      }
+    }
+    __syncthreads();
+  }
+  if (item && base) {
+    row[q * 2 + 1] = un[0];
+  } else if (item) {
+#pragma unroll
+    for (int mm = 0; mm < n1; ++mm) row[((ft + 1) * n2 + pp + n1 * mm) * 2 + 1] = un[mm];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused stage.  LOCAL: workgroups own whole hexahedra (triangle neighbours
-// are in the workgroup, T2 holds (p, u.n) base traces only); otherwise T2 is
-// the four-field trace array [K][Nfc][4] of all five faces, from which the
-// neighbour's p and n.u are read.
+// are in the workgroup, T2 holds (p, u.n) base traces only); otherwise T2
+// holds the (p, u.n) pairs of all five faces, [K][Nfc][2].
 // Waves per SIMD the stage is compiled for: N = 5 at three (168 registers,
 // some spilled to private memory) ran 30.3 -> 27.2 ms per stage at 64^3 x 6
 // when it was introduced; at N = 4 three waves measured slower (20.7 ->
@@ -541,10 +671,10 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
         const double* tp = T2 + ((int64_t)nb * n2 + q2) * 2;
         nbp = tp[0];
         nbun = tp[1];
-      } else {  // four fields
-        const double* tp = T2 + ((int64_t)nb * D::Nfc + sNb[le][0][2] * n2 + q2) * 4;
+      } else {  // pairs of all five faces
+        const double* tp = T2 + ((int64_t)nb * D::Nfc + sNb[le][0][2] * n2 + q2) * 2;
         nbp = tp[0];
-        nbun = -(nr[0] * tp[1] + nr[1] * tp[2] + nr[2] * tp[3]);
+        nbun = tp[1];
       }
     }
     double pp, unp, Fp, Pu;
@@ -586,9 +716,9 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
             nbp = sTT[loc][(nf - 1) * 2 * n2 + q2];
             nbun = sTT[loc][(nf - 1) * 2 * n2 + n2 + q2];
           } else {
-            const double* tp = T2 + ((int64_t)nb * D::Nfc + nf * n2 + q2) * 4;
+            const double* tp = T2 + ((int64_t)nb * D::Nfc + nf * n2 + q2) * 2;
             nbp = tp[0];
-            nbun = -(nrm[0] * tp[1] + nrm[1] * tp[2] + nrm[2] * tp[3]);
+            nbun = tp[1];
           }
         }
         double ppv, unp, Fp, Pu;
@@ -761,6 +891,9 @@ dgpyr_status check_n(const dgpyr_ctx& c, std::string& msg) {
                           "k_sf_stage", msg);
     }
   }
+  if ((st = check_kernel((const void*)k_sf_trace_all<N>, TraceAllShape<N>::THREADS,
+                         "k_sf_trace_all", msg)))
+    return st;
   if ((st = check_kernel((const void*)k_sf_stage<N, 0, false>, SfShape<N, false>::THREADS,
                          "k_sf_stage", msg)))
     return st;
@@ -779,7 +912,9 @@ hipError_t trace_n(const dgpyr_ctx& c, const double* U, double* T2, hipStream_t 
       return hipErrorInvalidValue;
     }
   } else {
-    return launch_trace_mfma(c, U, T2, s);  // four-field traces of all five faces
+    using TA = TraceAllShape<N>;
+    hipLaunchKernelGGL((k_sf_trace_all<N>), dim3((unsigned)((c.K + TA::E - 1) / TA::E)),
+                       dim3(TA::THREADS), 0, s, U, T2, c.sf, c.ops, c.mesh.verts, c.K);
   }
   return hipGetLastError();
 }

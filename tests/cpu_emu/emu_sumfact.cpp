@@ -21,26 +21,6 @@
 #include "host/refops.hpp"
 
 namespace {
-const dgpyr::RefOps* g_ops = nullptr;
-}  // namespace
-
-namespace dgpyr {
-// Host stand-in for the matrix-core trace kernel (kernels_mfma.hip, not built
-// here): four-field traces of all faces, T[K][Nfc][4] = V^f U.
-hipError_t launch_trace_mfma(const dgpyr_ctx& c, const double* U, double* T, hipStream_t) {
-  const RefOps& o = *g_ops;
-  for (int64_t e = 0; e < c.K; ++e)
-    for (int q = 0; q < o.Nfc; ++q)
-      for (int f = 0; f < 4; ++f) {
-        double acc = 0.0;
-        for (int n = 0; n < o.Np; ++n) acc += o.Vf[(size_t)q * o.Np + n] * U[(e * 4 + f) * o.Np + n];
-        T[(e * o.Nfc + q) * 4 + f] = acc;
-      }
-  return hipSuccess;
-}
-}  // namespace dgpyr
-
-namespace {
 
 template <typename T>
 bool rd(FILE* f, T* p, size_t n) {
@@ -80,7 +60,6 @@ int main(int argc, char** argv) {
   std::fclose(f);
 
   dgpyr::RefOps ops;
-  g_ops = &ops;
   char msg[256];
   if (!dgpyr::build_refops(N, ops, msg, sizeof msg)) {
     std::fprintf(stderr, "%s\n", msg);
@@ -132,7 +111,7 @@ int main(int argc, char** argv) {
   }
 
   // exactly sized buffers (AddressSanitizer flags any access past them)
-  std::vector<double> T2(c.sf_local ? (size_t)K * ops.Nfq * 2 : (size_t)K * ops.Nfc * 4);
+  std::vector<double> T2(c.sf_local ? (size_t)K * ops.Nfq * 2 : (size_t)K * ops.Nfc * 2);
   std::vector<double> out((size_t)K * 4 * Np), R(nsteps > 0 ? (size_t)K * 4 * Np : 0);
   if (nsteps == 0) {
     if (dgpyr::launch_sf_trace(c, U.data(), T2.data(), nullptr) != hipSuccess) return 4;
