@@ -84,9 +84,10 @@ struct SfDims {
   // need a region of their own
   static constexpr bool kSeparateC = 4 * n1 > n2;
   static constexpr int CC = kSeparateC ? 8 * n2 : 0;
-  static constexpr int kTables = 16 + 16 + 5 + 4 + 10;  // vertices, normals, rho c, material, ints
+  // vertices, normals, rho c, material, Jacobian coefficients, ints
+  static constexpr int kTables = 16 + 16 + 5 + 4 + 4 + 10;
   static constexpr int PER_ELEM = kTables + UD + AB + TT + CC;
-  static constexpr int PERM_BYTES = 10 * n2 * 4;
+  static constexpr int PERM_BYTES = 10 * n2 * 4 + Np * 4;  // permutations, padded positions
   // one-dimensional factors read with lane-dependent indices, staged in LDS
   // once per workgroup: l^k_i(x_p), d/da l^k_i(x_p) [k][p][i], l^k_i(-1, +1)
   // [k][s][i]
@@ -439,6 +440,8 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   __shared__ double sTT[E][D::TT];
   __shared__ double sCC[D::kSeparateC ? E : 1][D::kSeparateC ? D::CC : 1];
   __shared__ int sPerm[10 * n2];
+  __shared__ int sPad[Np];       // position of coefficient n in the padded row layout [kj][i]
+  __shared__ double sJc[E][4];   // bilinear Jacobian coefficients (1, a, b, ab)
   __shared__ double sLa[D::n3], sDa[D::n3], sLe[2 * n2];
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
@@ -456,7 +459,16 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
     sM[le][x % 4] = le < ne ? mesh.mat[(e0 + le) * 4 + x % 4] : 0.0;
   }
   for (int x = tid; x < 10 * n2; x += NT) sPerm[x] = ops.perm[x];
+  // the coefficients pass through LDS in rows of N+1 (row kj = (k, j) holds
+  // u_ijk at i, zeros beyond i = k), so that the a-direction needs no masks
+  for (int n = tid; n < Np; n += NT) {
+    int k, j, i;
+    kji_split<N>(n, k, j, i);
+    sPad[n] = (kjofs(k) + j) * n1 + i;
+  }
+  for (int x = tid; x < E * D::UD; x += NT) sUD[x / D::UD][x % D::UD] = 0.0;
   __syncthreads();
+  for (int x = tid; x < E; x += NT) pyr_jac_coeffs(sX[x], sJc[x]);
   for (int x = tid; x < E * 5; x += NT) {
     const int le = x / 5, f = x % 5;
     int nb = -1, loc = -1, nf = 0, prow = 0;
@@ -512,7 +524,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   constexpr int LD = (E * Np + NT - 1) / NT;  // coefficients each thread stages
   for (int x = tid; x < E * Np; x += NT) {
     const int l = x / Np, n = x % Np;
-    sUD[l][n] = l < ne ? U[((e0 + l) * 4 + 1) * Np + n] : 0.0;
+    sUD[l][sPad[n]] = l < ne ? U[((e0 + l) * 4 + 1) * Np + n] : 0.0;
   }
   __syncthreads();
 #pragma unroll
@@ -533,19 +545,14 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       const int kj = rem / n1, pp = rem % n1;
       int k, j;
       kj_split<N>(kj, k, j);
-      const double* u = sUD[l] + kofs(k) + j * (k + 1);
+      const double* u = sUD[l] + kj * n1;  // padded row: zeros beyond i = k
       const double* La = sLa + (k * n1 + pp) * n1;
       const double* Da = sDa + (k * n1 + pp) * n1;
-      // all n1 terms without branches: the factor tables hold zeros beyond
-      // i = k, and the row's neighbours in LDS (read in bounds) are masked
-      double uu[n1];
-#pragma unroll
-      for (int i = 0; i < n1; ++i) uu[i] = i <= k ? u[i] : 0.0;
       double a = 0.0, ad = 0.0;
 #pragma unroll
       for (int i = 0; i < n1; ++i) {
-        a += La[i] * uu[i];
-        ad += Da[i] * uu[i];
+        a += La[i] * u[i];
+        ad += Da[i] * u[i];
       }
       sAB[l][kj * n1 + pp] = a;
       sAB[l][KJ * n1 + kj * n1 + pp] = ad;
@@ -555,7 +562,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
         const double* Le = sLe + (k * 2 + sd) * n1;
         double ae = 0.0;
 #pragma unroll
-        for (int i = 0; i < n1; ++i) ae += Le[i] * uu[i];
+        for (int i = 0; i < n1; ++i) ae += Le[i] * u[i];
         sAB[l][2 * KJ * n1 + kj * 2 + sd] = ae;
       }
     }
@@ -564,7 +571,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
 #pragma unroll
       for (int q = 0; q < LD; ++q) {
         const int x = tid + q * NT;
-        if (x < E * Np) sUD[x / Np][x % Np] = nxt[q];
+        if (x < E * Np) sUD[x / Np][sPad[x % Np]] = nxt[q];
       }
     }
     // b- and c-directions, metric and projection along c, per column
@@ -764,7 +771,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
 #pragma unroll
   for (int q = 0; q < LD; ++q) {
     const int x = tid + q * NT, l = x / Np, n = x % Np;
-    minv[q] = x < ne * Np ? 1.0 / (pyr_jac(sX[l], ops.na[n], ops.nb[n]) * ops.wwc[n]) : 0.0;
+    minv[q] = x < ne * Np ? 1.0 / (pyr_jac_eval(sJc[l], ops.na[n], ops.nb[n]) * ops.wwc[n]) : 0.0;
   }
 #pragma unroll
   for (int fld = 0; fld < 4; ++fld) {
