@@ -763,6 +763,42 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
     }
   }
 
+  // ---- lift sums of the folded triangle fluxes, shared by the coefficients
+  // of a row: Tl[ty][face][kj] = sum_p l^k_r(x_p) cc[face][ty][k][p] with r = j
+  // for the a = -1, +1 faces and r = i for the b = -1, +1 faces (both the row
+  // index of kj = (k, r)); ty 0 lifts the pressure flux, 1 the velocity one.
+  // They replace the folded fluxes in the trace region.
+  __syncthreads();
+  {
+    constexpr int TI = 8 * KJ;                   // sums per element
+    constexpr int LT = (E * TI + NT - 1) / NT;  // sums per thread
+    double tv[LT];
+#pragma unroll
+    for (int q = 0; q < LT; ++q) {
+      const int x = tid + q * NT;
+      tv[q] = 0.0;
+      if (x < ne * TI) {
+        const int l = x / TI, rem = x % TI;
+        const int tf = rem / KJ, kj = rem % KJ, ty = tf / 4, face = tf % 4;
+        int k, r;
+        kj_split<N>(kj, k, r);
+        const double* cc = (D::kSeparateC ? (const double*)sCC[l] : (const double*)sTT[l]) +
+                           face * 2 * n2 + ty * n2 + k * n1;
+        const double* Lr = sLa + k * n2 + r;  // l^k_r(x_p) at p * n1
+        double acc = 0.0;
+#pragma unroll
+        for (int pp = 0; pp < n1; ++pp) acc += Lr[pp * n1] * cc[pp];
+        tv[q] = acc;
+      }
+    }
+    __syncthreads();  // every folded flux read before the sums replace them
+#pragma unroll
+    for (int q = 0; q < LT; ++q) {
+      const int x = tid + q * NT;
+      if (x < ne * TI) sTT[x / TI][x % TI] = tv[q];
+    }
+  }
+
   // ---- projection, one field at a time: b-direction, then a-direction with
   // the triangle lifts, inverse mass, material and the RK stage.  The inverse
   // mass diagonal of this thread's coefficients is evaluated once for the
@@ -817,18 +853,11 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       kji_split<N>(n, k, j, i);
       const double* La_k = sLa + k * n2;  // [p][i]
       const double* Dk = sUD[l] + (kjofs(k) + j) * n1;
-      const double* cc = D::kSeparateC ? (const double*)sCC[l] : (const double*)sTT[l];
-      const int ty = fld == 0 ? 0 : 1;
-      double v = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
+      const double* Tl = sTT[l] + (fld == 0 ? 0 : 4 * KJ) + kjofs(k);
+      double v = 0.0;
 #pragma unroll
-      for (int pp = 0; pp < n1; ++pp) {
-        const double li = La_k[pp * n1 + i], lj = La_k[pp * n1 + j];
-        v += li * Dk[pp];
-        t1 += lj * cc[0 * 2 * n2 + ty * n2 + k * n1 + pp];
-        t2 += lj * cc[1 * 2 * n2 + ty * n2 + k * n1 + pp];
-        t3 += li * cc[2 * 2 * n2 + ty * n2 + k * n1 + pp];
-        t4 += li * cc[3 * 2 * n2 + ty * n2 + k * n1 + pp];
-      }
+      for (int pp = 0; pp < n1; ++pp) v += La_k[pp * n1 + i] * Dk[pp];
+      const double t1 = Tl[j], t2 = Tl[KJ + j], t3 = Tl[2 * KJ + i], t4 = Tl[3 * KJ + i];
       const double* Le_k = sLe + k * 2 * n1;  // [side][i]
       double s1 = 1.0, s2 = 1.0, s3 = 1.0, s4 = 1.0;
       if (fld > 0) {
