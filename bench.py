@@ -343,7 +343,8 @@ def batch_bench(args):
     hexes per side, x 6 pyramids) and order (N ~ U{2..6}), per-element c^2 ~
     U[0.5, 2], one Ricker point source (f0 = 10) at a random location each;
     all advanced together (per-problem CFL time steps) through one captured
-    step graph.  Prints one JSON line."""
+    step graph, then the same problems one at a time for comparison.  Prints
+    one JSON line."""
     import torch
 
     import paper_1502_07703_amd as dg
@@ -379,6 +380,28 @@ def batch_bench(args):
         sys.exit(1)
     dof = sum(4 * sl["Np"] * sl["nelems"] for sl in b.slots)
     nel = sum(sl["nelems"] for sl in b.slots)
+    b.close()
+    del U, R
+    torch.cuda.empty_cache()
+    # the same problems one at a time, each in a context of its own with the
+    # sum-factorised FP64 kernels and the same steps: the rate the batch
+    # replaces
+    t_single = 0.0
+    for p in probs:
+        with dg.Solver(p["xyz"], p["e2v"], p["N"], rho=p["rho"], kappa=p["kappa"],
+                       sources=p["sources"], sum_factorized=True) as s1:
+            dt1 = s1.stable_dt(0.5)
+            U1, R1 = s1.empty_state().zero_(), s1.empty_state().zero_()
+            s1.step(U1, R1, dt1, args.warmup)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s1.step(U1, R1, dt1, args.steps, t0=args.warmup * dt1)
+            torch.cuda.synchronize()
+            t_single += time.perf_counter() - t1
+            del U1, R1
+    single = dof * 5 * args.steps / t_single / 1e9
+    print(f"[batch] batched {dof * 5 * args.steps / wall / 1e9:.2f}, one problem at a time "
+          f"{single:.2f} GDOF-stages/s", file=sys.stderr, flush=True)
     out = {"metric": "GDOF·stages/s, batched independent problems", "value":
            dof * 5 * args.steps / wall / 1e9, "unit": "GDOF·stages/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
@@ -388,8 +411,10 @@ def batch_bench(args):
                                   "pyramids, N ~ U{2..6}, c^2 ~ U[0.5,2] per element, one Ricker "
                                   "source each, per-problem CFL 0.5 time steps",
                       "problems": len(probs), "nelems": nel, "dof": dof, "groups": b.ngroups,
-                      "tuned_shapes": chosen, "setup_s": t_setup}}
-    b.close()
+                      "tuned_shapes": chosen, "setup_s": t_setup},
+           "one_problem_at_a_time": {"value": single, "unit": "GDOF·stages/s",
+                                     "kernels": "sum-factorised FP64, one context per problem",
+                                     "batch_speedup": dof * 5 * args.steps / wall / 1e9 / single}}
     print(json.dumps(out), flush=True)
 
 
