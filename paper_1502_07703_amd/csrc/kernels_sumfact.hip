@@ -413,13 +413,15 @@ __global__ __launch_bounds__((TraceAllShape<N>::THREADS)) void k_sf_trace_all(
 // Fused stage.  LOCAL: workgroups own whole hexahedra (triangle neighbours
 // are in the workgroup, T2 holds (p, u.n) base traces only); otherwise T2
 // holds the (p, u.n) pairs of all five faces, [K][Nfc][2].
-// Waves per SIMD the stage is compiled for: N = 5 at three (168 registers,
-// some spilled to private memory) ran 30.3 -> 27.2 ms per stage at 64^3 x 6
-// when it was introduced; at N = 4 three waves measured slower (20.7 ->
-// 22.5 ms at 64^3 x 6), and the other orders are left to the compiler.
+// Waves per SIMD the stage is compiled for: three at N = 5 (whole
+// hexahedra, three workgroups per CU; 30.3 -> 27.2 ms per stage at 64^3 x 6
+// when it was introduced) and N = 6 (general variant, 5 elements per
+// workgroup, three workgroups per CU: 32.3 -> 28.7 ms); at N = 4 three waves
+// measured slower (20.7 -> 22.5 ms), and the other orders are left to the
+// compiler.
 template <int N>
 struct SfWaves {
-  static constexpr int value = N == 5 ? 3 : 1;
+  static constexpr int value = N == 5 || N == 6 ? 3 : 1;
 };
 
 template <int N, int MODE, bool LOCAL>
