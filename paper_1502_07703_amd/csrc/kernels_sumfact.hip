@@ -109,7 +109,9 @@ struct SfDims {
   }
   static constexpr int free_elems() {
     int best = 1;
-    for (int E = 1; E * n2 <= 256 && bytes(E) <= kLdsBudget; ++E) best = E;
+    // (N = 7: two elements, two waves, four workgroups per CU: 51.0 -> 49.6
+    // ms against four elements at 64^3 x 6)
+    for (int E = 1; E * n2 <= (N == 7 ? 128 : 256) && bytes(E) <= kLdsBudget; ++E) best = E;
     return best;
   }
 };
