@@ -253,13 +253,14 @@ __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
   constexpr int n1 = D::n1, n2 = D::n2, Np = D::Np, E = TS::E, NT = TS::THREADS, PTS = TS::PTS;
   __shared__ double sU[E][4 * Np];
   __shared__ double sX[E][16];
-  __shared__ double sLa[D::n3], sDa[D::n3], sLe[2 * n2];
+  __shared__ double sLa[D::n3], sLe[2 * n2];
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(K - e0 < E ? K - e0 : E);
   for (int x = tid; x < ne * 4 * Np; x += NT) sU[x / (4 * Np)][x % (4 * Np)] = U[e0 * 4 * Np + x];
   for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
-  stage_tables<N>(sf, sLa, sDa, sLe, tid, NT);
+  for (int x = tid; x < D::n3; x += NT) sLa[x] = sf.La[x];
+  for (int x = tid; x < 2 * n2; x += NT) sLe[x] = sf.Le[x];
   __syncthreads();
   for (int x = tid; x < ne * PTS; x += NT) {
     const int le = x / PTS, q = x % PTS;
