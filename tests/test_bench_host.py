@@ -63,3 +63,22 @@ def test_cpu_baseline_closure_holds_every_face_neighbour():
     full = AcousticDG(xyz, e2v, 2, elems=S).rhs(U)
     part = AcousticDG(xs, es, 2, elems=loc).rhs(U[sub])
     assert np.abs(full - part).max() <= 1e-14 * np.abs(full).max()
+
+
+def test_headline_takes_the_faster_fp64_path():
+    dense = {"value": 17.0, "roofline": {"frac": 0.5}}
+    sf = {"value": 31.0, "roofline": {"frac": 0.2}}
+    res, path = bench.fp64_headline(dense, {"fp64_sum_factorized": sf})
+    assert res is sf and path == "sumfact"
+    res, path = bench.fp64_headline({"value": 40.0}, {"fp64_sum_factorized": sf})
+    assert res["value"] == 40.0 and path == "fused"
+
+
+def test_sum_factorised_work_is_below_the_dense_work():
+    # the collapsed tensor structure costs O(N^4) per element against O(N^6)
+    for N in range(2, 9):
+        Fsf, Bsf = bench.sf_work("stage", N, local=True)
+        Fd, Bd = bench.kernel_work("stage", N)
+        assert Fsf < Fd and Bsf <= Bd
+    assert bench.work("stage", 5, "sumfact") == bench.sf_work("stage", 5, local=True)
+    assert bench.work("stage", 6, "sumfact") == bench.sf_work("stage", 6, local=False)
