@@ -254,11 +254,13 @@ __global__ __launch_bounds__(kBlock, Bf16Waves<N>::value) void k_stage_bf16(cons
   if (e >= mesh.K) return;
   const double kap = mesh.mat[e * 4 + 0], irho = mesh.mat[e * 4 + 1];
   const double dte = dt * mesh.mat[e * 4 + 3];
+  double jc[4];  // J is bilinear in (a, b): four coefficients per element
+  pyr_jac_coeffs(xv, jc);
 #pragma unroll
   for (int u = 0; u < TT::NIT; ++u) {
     const int i = 16 * u + dq;
     if (i >= TT::Np) continue;
-    const double minv = 1.0 / (pyr_jac(xv, ops.na[i], ops.nb[i]) * ops.wwc[i]);
+    const double minv = 1.0 / (pyr_jac_eval(jc, ops.na[i], ops.nb[i]) * ops.wwc[i]);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double acc = (double)z[u][v] - (v == 0 ? source_term<TT::Np>(mesh, e, i) : 0.0);

@@ -29,20 +29,21 @@
 // pairs of all five faces, [K][Nfc][2], and the stage reads its neighbours'
 // from HBM.
 //
-// Work shape.  A workgroup owns E elements and one thread per (element, a, b)
-// column.  The four fields are processed one at a time through LDS: the
-// a-direction contraction at the a-points and at a = -1, +1 (all threads),
-// then per column the b- and c-direction contractions, the FP64 metric and
-// the projection onto the c factors, accumulated in registers across the
-// fields, and beside them the triangle traces as b- and c-contractions of the
-// a-direction results; after the face fluxes
-// the projection is finished field by field (b-direction, then a-direction
-// with the triangle lifts, inverse mass and the LSRK stage).  LDS stays under
-// 60 KiB per workgroup and no kernel keeps arrays in private memory (the
-// N = 5 stage, compiled for three waves per SIMD, spills a few registers, 52
-// bytes per lane); setup
-// checks LDS, private memory and block size (hipFuncGetAttributes against the
-// device's limits) before the first launch.
+// Work shape.  A workgroup owns E elements (at most 256 columns) and one
+// thread per (element, a, b) column.  The four fields are processed one at a
+// time through LDS, the velocities first: the a-direction contraction at the
+// a-points and at a = -1, +1 (all threads), then per column the b- and
+// c-direction contractions, the FP64 metric and the projection onto the c
+// factors, accumulated in registers across the fields, and beside them the
+// triangle traces as b- and c-contractions of the a-direction results; the
+// next field's coefficients are loaded while the current one is contracted.
+// After the face fluxes (folded along c, then summed once per row into the
+// triangle lift sums) the projection is finished field by field
+// (b-direction, then a-direction with the triangle lifts, inverse mass and
+// the LSRK stage, the RK state loaded ahead).  LDS stays under 60 KiB per
+// workgroup and no kernel keeps arrays in private memory; setup checks LDS,
+// private memory and block size (hipFuncGetAttributes against the device's
+// limits) before the first launch.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
