@@ -94,7 +94,8 @@ typedef struct {
                                            of O(N^6) flops per element; on meshes of
                                            hexahedra split into 6 pyramids (groups of
                                            6 consecutive elements around one apex)
-                                           the triangle-face traces stay on chip.
+                                           and N <= 5 the triangle-face traces stay
+                                           on chip.
                                            FP64 precision form only (else
                                            E_UNSUPPORTED); E_UNSUPPORTED too if a
                                            kernel's resources exceed the device's */
