@@ -88,7 +88,8 @@ struct SfDims {
   // vertices, normals, rho c, material, Jacobian coefficients, ints
   static constexpr int kTables = 16 + 16 + 5 + 4 + 4 + 10;
   static constexpr int PER_ELEM = kTables + UD + AB + TT + CC;
-  static constexpr int PERM_BYTES = 10 * n2 * 4 + Np * 4;  // permutations, padded positions
+  // permutations, padded positions, index tables
+  static constexpr int PERM_BYTES = 10 * n2 * 4 + 2 * Np * 4 + KJ * 4;
   // one-dimensional factors read with lane-dependent indices, staged in LDS
   // once per workgroup: l^k_i(x_p), d/da l^k_i(x_p) [k][p][i], l^k_i(-1, +1)
   // [k][s][i]
@@ -447,6 +448,8 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   __shared__ double sCC[D::kSeparateC ? E : 1][D::kSeparateC ? D::CC : 1];
   __shared__ int sPerm[10 * n2];
   __shared__ int sPad[Np];       // position of coefficient n in the padded row layout [kj][i]
+  __shared__ int sKJ[KJ];        // (k, j) of a row index kj, packed k | j << 8
+  __shared__ int sKJI[Np];       // (k, j, i) of a coefficient index, packed k | j << 8 | i << 16
   __shared__ double sJc[E][4];   // bilinear Jacobian coefficients (1, a, b, ab)
   __shared__ double sLa[D::n3], sDa[D::n3], sLe[2 * n2];
   const int tid = threadIdx.x;
@@ -471,6 +474,12 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
     int k, j, i;
     kji_split<N>(n, k, j, i);
     sPad[n] = (kjofs(k) + j) * n1 + i;
+    sKJI[n] = k | j << 8 | i << 16;
+  }
+  for (int kj = tid; kj < KJ; kj += NT) {
+    int k, j;
+    kj_split<N>(kj, k, j);
+    sKJ[kj] = k | j << 8;
   }
   for (int x = tid; x < E * D::UD; x += NT) sUD[x / D::UD][x % D::UD] = 0.0;
   __syncthreads();
@@ -549,8 +558,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
     for (int x = tid; x < ne * KJ * n1; x += NT) {
       const int l = x / (KJ * n1), rem = x % (KJ * n1);
       const int kj = rem / n1, pp = rem % n1;
-      int k, j;
-      kj_split<N>(kj, k, j);
+      const int kjc = sKJ[kj], k = kjc & 255, j = kjc >> 8;
       const double* u = sUD[l] + kj * n1;  // padded row: zeros beyond i = k
       const double* La = sLa + (k * n1 + pp) * n1;
       const double* Da = sDa + (k * n1 + pp) * n1;
@@ -786,8 +794,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       if (x < ne * TI) {
         const int l = x / TI, rem = x % TI;
         const int tf = rem / KJ, kj = rem % KJ, ty = tf / 4, face = tf % 4;
-        int k, r;
-        kj_split<N>(kj, k, r);
+        const int kjc = sKJ[kj], k = kjc & 255, r = kjc >> 8;
         const double* cc = (D::kSeparateC ? (const double*)sCC[l] : (const double*)sTT[l]) +
                            face * 2 * n2 + ty * n2 + k * n1;
         const double* Lr = sLa + k * n2 + r;  // l^k_r(x_p) at p * n1
@@ -841,8 +848,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
     for (int x = tid; x < ne * KJ * n1; x += NT) {
       const int l = x / (KJ * n1), rem = x % (KJ * n1);
       const int kj = rem / n1, pp = rem % n1;
-      int k, j;
-      kj_split<N>(kj, k, j);
+      const int kjc = sKJ[kj], k = kjc & 255, j = kjc >> 8;
       const double* B = sAB[l] + k * n2 + pp;
       double acc = 0.0;
 #pragma unroll
@@ -855,8 +861,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       const int x = tid + q * NT;
       if (x >= ne * Np) continue;
       const int l = x / Np, n = x % Np;
-      int k, j, i;
-      kji_split<N>(n, k, j, i);
+      const int kc = sKJI[n], k = kc & 255, j = (kc >> 8) & 255, i = kc >> 16;
       const double* La_k = sLa + k * n2;  // [p][i]
       const double* Dk = sUD[l] + (kjofs(k) + j) * n1;
       const double* Tl = sTT[l] + (fld == 0 ? 0 : 4 * KJ) + kjofs(k);
