@@ -317,6 +317,7 @@ __global__ __launch_bounds__((TraceAllShape<N>::THREADS)) void k_sf_trace_all(
   __shared__ double sX[E][16];
   __shared__ double sN[E][4][4];  // triangle faces: unit normal, sJ
   __shared__ double sLa[D::n3], sLe[2 * n2];
+  __shared__ int sKJ[KJ];  // (k, j) of a row index kj, packed k | j << 8
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(K - e0 < E ? K - e0 : E);
@@ -324,6 +325,11 @@ __global__ __launch_bounds__((TraceAllShape<N>::THREADS)) void k_sf_trace_all(
   for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
   for (int x = tid; x < D::n3; x += NT) sLa[x] = sf.La[x];
   for (int x = tid; x < 2 * n2; x += NT) sLe[x] = sf.Le[x];
+  for (int kj = tid; kj < KJ; kj += NT) {
+    int k, j;
+    kj_split<N>(kj, k, j);
+    sKJ[kj] = k | j << 8;
+  }
   __syncthreads();
   for (int x = tid; x < ne * 4; x += NT) {
     const int l = x / 4, f = x % 4 + 1;
@@ -346,8 +352,7 @@ __global__ __launch_bounds__((TraceAllShape<N>::THREADS)) void k_sf_trace_all(
     for (int x = tid; x < ne * KJ * n1; x += NT) {
       const int el = x / (KJ * n1), rem = x % (KJ * n1);
       const int kj = rem / n1, p = rem % n1;
-      int k, j;
-      kj_split<N>(kj, k, j);
+      const int kjc = sKJ[kj], k = kjc & 255, j = kjc >> 8;
       const double* u = sU[el] + fld * Np + kofs(k) + j * (k + 1);
       double uu[n1];
 #pragma unroll
