@@ -460,6 +460,10 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(mesh.K - e0 < E ? mesh.K - e0 : E);
+  // this workgroup's rows of the state and residual: 32-bit offsets below
+  const double* Uw = U + e0 * 4 * Np;
+  double* ow = out + e0 * 4 * Np;
+  double* Rw = MODE == 1 ? R + e0 * 4 * Np : nullptr;
 
   // ---- tables: vertices, face neighbours, triangle normals, permutations,
   // one-dimensional factors
@@ -544,7 +548,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
   constexpr int LD = (E * Np + NT - 1) / NT;  // coefficients each thread stages
   for (int x = tid; x < E * Np; x += NT) {
     const int l = x / Np, n = x % Np;
-    sUD[l][sPad[n]] = l < ne ? U[((e0 + l) * 4 + 1) * Np + n] : 0.0;
+    sUD[l][sPad[n]] = l < ne ? Uw[(l * 4 + 1) * Np + n] : 0.0;
   }
   __syncthreads();
 #pragma unroll
@@ -556,7 +560,7 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
 #pragma unroll
       for (int q = 0; q < LD; ++q) {
         const int x = tid + q * NT, l = x / Np, n = x % Np;
-        nxt[q] = (x < E * Np && l < ne) ? U[((e0 + l) * 4 + nfld) * Np + n] : 0.0;
+        nxt[q] = (x < E * Np && l < ne) ? Uw[(l * 4 + nfld) * Np + n] : 0.0;
       }
     }
     // a-direction: A[kj][p] = sum_i l_i(a_p) u_ijk, A'[kj][p] with l'_i(a_p)
@@ -838,9 +842,9 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
         const int x = tid + q * NT;
         uo[q] = ro[q] = 0.0;
         if (x < ne * Np) {
-          const int64_t idx = ((e0 + x / Np) * 4 + fld) * Np + x % Np;
-          uo[q] = out[idx];
-          if (ra != 0.0) ro[q] = R[idx];
+          const int idx = (x / Np * 4 + fld) * Np + x % Np;
+          uo[q] = ow[idx];
+          if (ra != 0.0) ro[q] = Rw[idx];
         }
       }
     }
@@ -885,14 +889,14 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
       v += s1 * Le_k[i] * t1 + s2 * Le_k[n1 + i] * t2 + s3 * Le_k[j] * t3 + s4 * Le_k[n1 + j] * t4;
       const int64_t el = e0 + l;
       if (fld == 0) v -= source_term<Np>(mesh, el, n);
-      const int64_t idx = (el * 4 + fld) * Np + n;
+      const int idx = (l * 4 + fld) * Np + n;
       const double rhs = -sM[l][fld == 0 ? 0 : 1] * minv[q] * v;
       if constexpr (MODE == 0) {
-        out[idx] = rhs;
+        ow[idx] = rhs;
       } else {  // R <- ra R + dt rhs, U <- U + rb R (finish_coeff with the loads above)
         const double rn = ra * ro[q] + dt * sM[l][3] * rhs;
-        R[idx] = rn;
-        out[idx] = uo[q] + rb * rn;
+        Rw[idx] = rn;
+        ow[idx] = uo[q] + rb * rn;
       }
     }
     __syncthreads();
