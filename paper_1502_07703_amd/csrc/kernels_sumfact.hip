@@ -618,17 +618,17 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
         sb[k] = xb;
         tb[fld] += sf.Gb[k] * x0;
       }
+      if (fld == 0) {
 #pragma unroll
-      for (int r = 0; r < n1; ++r) {
-        double dr = 0.0, ds = 0.0, dtp = 0.0;
+        for (int r = 0; r < n1; ++r) {
+          double dr = 0.0, ds = 0.0, dtp = 0.0;
 #pragma unroll
-        for (int k = 0; k < n1; ++k) {
-          dr += sf.Gt[r * n1 + k] * sa[k];
-          ds += sf.Gt[r * n1 + k] * sb[k];
-          dtp += sf.Gp[r * n1 + k] * s0[k];
-        }
-        const double dtt = dtp + ha * dr + hb * ds;
-        if (fld == 0) {
+          for (int k = 0; k < n1; ++k) {
+            dr += sf.Gt[r * n1 + k] * sa[k];
+            ds += sf.Gt[r * n1 + k] * sb[k];
+            dtp += sf.Gp[r * n1 + k] * s0[k];
+          }
+          const double dtt = dtp + ha * dr + hb * ds;
           // Q_{u_d} = w sum_rho adj[rho][d] d_rho p, projected onto g_k(c_r)
           const double w = wab * sf.wc[r];
 #pragma unroll
@@ -637,9 +637,26 @@ __global__ __launch_bounds__((SfShape<N, LOCAL>::THREADS), (SfWaves<N>::value)) 
 #pragma unroll
             for (int k = 0; k < n1; ++k) bacc[1 + d][k] += sf.G[r * n1 + k] * q;
           }
-        } else {
-          const int d = fld - 1;
-          qp[r] += adj[d] * dr + adj[3 + d] * ds + adj[6 + d] * dtt;
+        }
+      } else {
+        // the d-th term of div u, sum_rho adj[rho][d] d_rho u_d with
+        // d_t = d_t' + (1+a)/2 d_r + (1+b)/2 d_s, folded into the column's
+        // constants before the c-direction: one combined c-contraction
+        const int d = fld - 1;
+        const double ca = adj[d] + ha * adj[6 + d], cb = adj[3 + d] + hb * adj[6 + d];
+        const double ct = adj[6 + d];
+        double tk[n1];
+#pragma unroll
+        for (int k = 0; k < n1; ++k) tk[k] = ca * sa[k] + cb * sb[k];
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+          double g1 = 0.0, g2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < n1; ++k) {
+            g1 += sf.Gt[r * n1 + k] * tk[k];
+            g2 += sf.Gp[r * n1 + k] * s0[k];
+          }
+          qp[r] += g1 + ct * g2;
         }
       }
     }
