@@ -1,8 +1,8 @@
 """Build and run the CPU emulation of the sum-factorised kernels.
 
-The library's kernel source is compiled for the host with g++ and
-AddressSanitizer against the stand-in hip/hip_runtime.h of this folder
-(every work item an OS thread, workgroup barriers real barriers), so that its
+The library's kernel source is compiled for the host with g++, AddressSanitizer
+and UndefinedBehaviorSanitizer against the stand-in hip/hip_runtime.h of this
+folder (every work item an OS thread, workgroup barriers real barriers), so that its
 indexing and its results can be checked without a GPU.  Test infrastructure
 only.
 
@@ -30,22 +30,27 @@ SOURCES = [os.path.join(HERE, "emu_sumfact.cpp"), os.path.join(CSRC, "host", "re
            os.path.join(CSRC, "host", "mesh.cpp")]
 DEPS = SOURCES + [os.path.join(CSRC, n) for n in
                   ("kernels_sumfact.hip", "context.hpp", "flux.hpp", "geom.hpp")] + \
-    [os.path.join(HERE, "hip", "hip_runtime.h")]
+    [os.path.join(HERE, "hip", "hip_runtime.h"), os.path.abspath(__file__)]
 
 
 def build(force: bool = False) -> str:
-    """Compile the emulator (g++, AddressSanitizer) if it is missing or stale."""
+    """Compile the emulator (g++, address and undefined-behaviour sanitizers) if it is missing or stale."""
     if not force and os.path.exists(EXE):
         t = os.path.getmtime(EXE)
         if all(os.path.getmtime(d) <= t for d in DEPS):
             return EXE
     os.makedirs(os.path.dirname(EXE), exist_ok=True)
-    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
+    tmp = f"{EXE}.{os.getpid()}.tmp"
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
            "-pthread", f"-I{HERE}", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", *SOURCES,
-           "-o", EXE]
+           "-o", tmp]
+    # Parallel test workers may build at once: each writes its own file and
+    # renames it into place, so no worker ever runs a half-written binary.
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("emulator build failed:\n" + r.stderr[-4000:])
+    os.replace(tmp, EXE)
     return EXE
 
 
@@ -96,7 +101,7 @@ def main():
     out, local = run(xyz, e2v, a.N, U, edge_blocks=a.edge_blocks)
     part = f"first and last {a.edge_blocks} workgroups" if a.edge_blocks else "every workgroup"
     print(f"k1d={a.k1d} N={a.N} K={e2v.shape[0]} ({part}): finite={bool(np.isfinite(out).all())} "
-          f"whole-hexahedron={local} {time.time() - t:.1f} s, no AddressSanitizer report")
+          f"whole-hexahedron={local} {time.time() - t:.1f} s, no sanitizer report")
 
 
 if __name__ == "__main__":
