@@ -106,6 +106,12 @@ typedef struct {
                                            points, so that no later call allocates
                                            device memory                          */
 
+#define DGPYR_FLAG_WATCHDOG 16u         /* after every LSRK step of dgpyr_step and
+                                           dgpyr_step_timed, check the state for
+                                           NaN or infinite entries (one extra read
+                                           of U per step, no change to the results);
+                                           read the outcome with dgpyr_watchdog  */
+
 #define DGPYR_MAX_RESERVED_RECEIVERS 4096
 
 typedef struct {
@@ -182,6 +188,17 @@ dgpyr_status dgpyr_step(dgpyr_ctx* ctx, double* U, double* R, double t0, double 
 dgpyr_status dgpyr_step_timed(dgpyr_ctx* ctx, double* U, double* R, double t0, double dt,
                               int32_t nsteps, void* stream, int32_t nk, double* kernel_ms,
                               int64_t* launches);
+
+/* Outcome of the NaN/Inf watchdog (contexts set up with DGPYR_FLAG_WATCHDOG):
+ * synchronises the stream, then sets *first_bad_step to -1 if every state
+ * checked since setup or the previous dgpyr_watchdog call was finite, else to
+ * the 0-based index, counted over the steps of those calls, of the first step
+ * after which the state held a NaN or an infinite entry; then starts a new
+ * count.  No physics of the method is involved: the paper's scheme is stable
+ * under the CFL rule of Section 4.3, and the check catches steps taken beyond
+ * it or corrupted input.  Errors: E_ARG (null pointer), E_STATE (context set up
+ * without the flag), E_HIP. */
+dgpyr_status dgpyr_watchdog(dgpyr_ctx* ctx, int64_t* first_bad_step, void* stream);
 
 /* Semicolon-separated names of the kernel kinds dgpyr_step launches, in the
  * order used by dgpyr_step_timed; the string lives as long as the context. */

@@ -94,11 +94,12 @@ class _HostMesh:
 
 
 def _opts(precision, alpha, reference_kernels=False, unfused=False, sum_factorized=False,
-          adjoint=False):
+          adjoint=False, watchdog=False):
     flags = (B.FLAG_REFERENCE_KERNELS if reference_kernels else 0) | \
         (B.FLAG_UNFUSED if unfused else 0) | \
         (B.FLAG_SUM_FACTORIZED if sum_factorized else 0) | \
-        (B.FLAG_ADJOINT if adjoint else 0)
+        (B.FLAG_ADJOINT if adjoint else 0) | \
+        (B.FLAG_WATCHDOG if watchdog else 0)
     return B.Opts(precision=B.PRECISION[precision], alpha=float(alpha), flags=flags)
 
 
@@ -108,11 +109,12 @@ class Solver:
     def __init__(self, xyz, e2v, N, rho=None, kappa=None, bc="wall", alpha=1.0,
                  precision="fp64", reference_kernels=False, unfused=False,
                  sum_factorized=False, groups_per_wave=0, sources=None, lds_operators=None,
-                 trace_groups=0, adjoint=False, stream=None):
+                 trace_groups=0, adjoint=False, watchdog=False, stream=None):
         L = B.lib()
         self._host = _HostMesh(xyz, e2v, rho, kappa, bc, sources)
         mesh = self._host.struct
-        opts = _opts(precision, alpha, reference_kernels, unfused, sum_factorized, adjoint)
+        opts = _opts(precision, alpha, reference_kernels, unfused, sum_factorized, adjoint,
+                     watchdog)
         handle = ctypes.c_void_p()
         st = L.dgpyr_setup(ctypes.byref(mesh), int(N), ctypes.byref(opts),
                            _stream_handle(stream) if stream is not None else None,
@@ -225,6 +227,16 @@ class Solver:
                                    _dptr(R, self.state_len, "R"), float(t0), float(dt),
                                    int(nsteps), _stream_handle(stream)), "dgpyr_step")
         return U, R
+
+    def watchdog(self, stream=None):
+        """NaN/Inf watchdog (Solver(..., watchdog=True)): -1 if every state
+        checked since the previous call was finite, else the 0-based index of
+        the first step, counted over the step calls since then, after which the
+        state held a non-finite entry.  Synchronises the stream."""
+        v = ctypes.c_int64()
+        B.check(B.lib().dgpyr_watchdog(self._h, ctypes.byref(v), _stream_handle(stream)),
+                "dgpyr_watchdog")
+        return v.value
 
     # -- initial data and errors ------------------------------------------------------
     def volume_points(self, stream=None):

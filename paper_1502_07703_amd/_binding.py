@@ -21,13 +21,14 @@ FLAG_REFERENCE_KERNELS = 1
 FLAG_UNFUSED = 2
 FLAG_SUM_FACTORIZED = 4
 FLAG_ADJOINT = 8
+FLAG_WATCHDOG = 16
 MAX_RESERVED_RECEIVERS = 4096
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Symbols the header declares; tests check that the library exports them all.
 EXPORTS = (
     "dgpyr_setup", "dgpyr_get_info", "dgpyr_stable_dt", "dgpyr_pack", "dgpyr_unpack", "dgpyr_rhs",
-    "dgpyr_step", "dgpyr_step_timed", "dgpyr_adjoint_rhs", "dgpyr_adjoint_rhs_noalloc",
+    "dgpyr_step", "dgpyr_step_timed", "dgpyr_watchdog", "dgpyr_adjoint_rhs", "dgpyr_adjoint_rhs_noalloc",
     "dgpyr_set_kappa",
     "dgpyr_set_receivers", "dgpyr_receivers_sample", "dgpyr_receivers_inject",
     "dgpyr_adjoint_step", "dgpyr_set_operator_staging", "dgpyr_set_trace_groups", "dgpyr_set_groups", "dgpyr_kernel_names", "dgpyr_host_reference",
@@ -150,6 +151,8 @@ def lib():
     L.dgpyr_set_operator_staging.restype = c_int32
     L.dgpyr_set_groups.argtypes = [c_void_p, c_int32]
     L.dgpyr_set_groups.restype = c_int32
+    L.dgpyr_watchdog.argtypes = [c_void_p, POINTER(c_int64), c_void_p]
+    L.dgpyr_watchdog.restype = c_int32
     L.dgpyr_kernel_names.argtypes = [c_void_p]
     L.dgpyr_kernel_names.restype = c_char_p
     L.dgpyr_host_reference.argtypes = [c_int32, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]

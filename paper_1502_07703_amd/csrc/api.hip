@@ -538,7 +538,8 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
   if (N < 0 || N > DGPYR_MAX_ORDER) return fail(DGPYR_E_ORDER, "N must be in [0, 8]");
   if (mesh->bc != DGPYR_BC_WALL && mesh->bc != DGPYR_BC_FREE) return fail(DGPYR_E_ARG, "bad bc");
   if (opts->flags & ~(uint32_t)(DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED |
-                                DGPYR_FLAG_SUM_FACTORIZED | DGPYR_FLAG_ADJOINT))
+                                DGPYR_FLAG_SUM_FACTORIZED | DGPYR_FLAG_ADJOINT |
+                                DGPYR_FLAG_WATCHDOG))
     return fail(DGPYR_E_ARG, "unknown flag bits");
   if ((opts->flags & DGPYR_FLAG_SUM_FACTORIZED) &&
       (opts->precision != DGPYR_FP64 || (opts->flags & (DGPYR_FLAG_REFERENCE_KERNELS | DGPYR_FLAG_UNFUSED))))
@@ -618,6 +619,11 @@ dgpyr_status setup_impl(const dgpyr_mesh* mesh, int32_t N, const dgpyr_opts* opt
     if (st != DGPYR_OK) st = fail(st, rmsg);
   }
   if (st == DGPYR_OK && (opts->flags & DGPYR_FLAG_ADJOINT)) st = reserve_adjoint(c);
+  if (st == DGPYR_OK && (opts->flags & DGPYR_FLAG_WATCHDOG)) {
+    const unsigned long long* pw = nullptr;
+    st = upload(c, std::vector<unsigned long long>(1, ~0ull), &pw, "watchdog");
+    c->watch = const_cast<unsigned long long*>(pw);
+  }
   if (st != DGPYR_OK) {
     free_ctx(c);
     return st;
@@ -697,6 +703,28 @@ dgpyr_status dgpyr_rhs(dgpyr_ctx* c, const double* U, double* dUdt, double t, vo
   return e == hipSuccess ? DGPYR_OK : hip_fail(e, "rhs launch");
 }
 
+// NaN/Inf check of the state after step n of the current call.
+static hipError_t watch_state(dgpyr_ctx* c, const double* U, int n, hipStream_t s) {
+  return dgpyr::launch_nonfinite(U, c->K * c->nfields * c->Np,
+                                 (unsigned long long)(c->watch_steps + n), c->watch, s);
+}
+
+dgpyr_status dgpyr_watchdog(dgpyr_ctx* c, int64_t* first_bad_step, void* stream) {
+  if (dgpyr_status s = check_ctx(c)) return s;
+  if (!first_bad_step) return fail(DGPYR_E_ARG, "first_bad_step is null");
+  if (!c->watch) return fail(DGPYR_E_STATE, "context set up without DGPYR_FLAG_WATCHDOG");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  unsigned long long v = 0;
+  const unsigned long long none = ~0ull;
+  e = hipMemcpy(&v, c->watch, sizeof v, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(c->watch, &none, sizeof none, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "watchdog copy");
+  c->watch_steps = 0;
+  *first_bad_step = v == none ? -1 : (int64_t)v;
+  return DGPYR_OK;
+}
+
 dgpyr_status dgpyr_step(dgpyr_ctx* c, double* U, double* R, double t0, double dt, int32_t nsteps,
                         void* stream) {
   if (dgpyr_status s = check_ctx(c)) return s;
@@ -717,7 +745,9 @@ dgpyr_status dgpyr_step(dgpyr_ctx* c, double* U, double* R, double t0, double dt
     }
     e = dgpyr::launch_clock(c->clock, 1.0, true, s);
     if (e != hipSuccess) return hip_fail(e, "clock");
+    if (c->watch && (e = watch_state(c, U, n, s)) != hipSuccess) return hip_fail(e, "watchdog");
   }
+  c->watch_steps += nsteps;
   return DGPYR_OK;
 }
 
@@ -749,7 +779,9 @@ dgpyr_status dgpyr_step_timed(dgpyr_ctx* c, double* U, double* R, double t0, dou
     }
     ec = dgpyr::launch_clock(c->clock, 1.0, true, s);
     if (ec != hipSuccess) return hip_fail(ec, "clock");
+    if (c->watch && (ec = watch_state(c, U, n, s)) != hipSuccess) return hip_fail(ec, "watchdog");
   }
+  c->watch_steps += nsteps;
   tm.drain();
   if (tm.err != hipSuccess) return hip_fail(tm.err, "event timing");
   hipError_t e = hipStreamSynchronize(s);

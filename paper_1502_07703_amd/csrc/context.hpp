@@ -165,6 +165,9 @@ struct dgpyr_ctx {
   double* T = nullptr;    // [K][Nfc][4] face traces
   double* vol = nullptr;  // [K][4][Np] volume contribution
   double* clock = nullptr;  // device step counter (source times)
+  unsigned long long* watch = nullptr;  // NaN/Inf watchdog: first bad step, or all
+                                        // ones; null without DGPYR_FLAG_WATCHDOG
+  int64_t watch_steps = 0;              // steps checked since the last query
   int nsrc = 0;
   int64_t device_bytes = 0;
   int device = 0;  // HIP device the context was set up on
@@ -187,6 +190,8 @@ hipError_t launch_surface(const dgpyr_ctx& c, int mode, const double* T, const d
 hipError_t launch_points(const dgpyr_ctx& c, double* xyz, double* wJ, hipStream_t s);
 hipError_t launch_clock(double* clock, double value, bool add, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t s);
+hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long step,
+                            unsigned long long* first_bad, hipStream_t s);
 // Transposed operator (kernels_adjoint.hip).
 hipError_t launch_adjoint_scale(const dgpyr_ctx& c, const double* lam, double* mu, hipStream_t s);
 hipError_t launch_adjoint(const dgpyr_ctx& c, const double* mu, const double* T, double* out,

@@ -75,6 +75,18 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double value) {
     x[i] = value;
 }
 
+// Watchdog: if any of x[0 .. n) is a NaN or an infinity (all exponent bits
+// set), lower *first_bad to step.  The minimum does not depend on the order of
+// the updates, so the outcome is deterministic; x is only read.
+__global__ void k_nonfinite(const double* __restrict__ x, int64_t n, unsigned long long step,
+                            unsigned long long* first_bad) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    bad |= ((__double_as_longlong(x[i]) >> 52) & 0x7ff) == 0x7ff;
+  if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicMin(first_bad, step);
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -84,6 +96,15 @@ hipError_t launch_fill(double* x, int64_t n, double value, hipStream_t s) {
   const int64_t nb = (n + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)(nb < 65536 ? nb : 65536)), dim3(kThreads), 0, s, x, n,
                      value);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const double* x, int64_t n, unsigned long long step,
+                            unsigned long long* first_bad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(kThreads), 0, s,
+                     x, n, step, first_bad);
   return hipGetLastError();
 }
 

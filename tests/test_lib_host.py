@@ -176,6 +176,9 @@ def test_setup_errors_before_device(B):
     import ctypes
     dt = ctypes.c_double(0.0)
     assert L.dgpyr_stable_dt(None, 0.5, ctypes.byref(dt)) == B.E_ARG
+    bad_step = ctypes.c_int64(0)
+    assert L.dgpyr_watchdog(None, ctypes.byref(bad_step), None) != 0
+    assert L.dgpyr_watchdog(None, None, None) != 0
     assert L.dgpyr_batch_tune(None, None, None, 1, None, None) != 0
 
 
