@@ -246,8 +246,12 @@ __device__ __forceinline__ double face_value(const double* u, int f, int p, int 
   return val;
 }
 
+// Four waves per SIMD (at most 128 registers, no spills up to N = 5): the
+// kernel waits on memory most of its time, and the compiler's own choice
+// (138 registers at N = 5) leaves three (2.65 -> 2.61 ms at 64^3 x 6, N = 5;
+// five waves spill and take 3.73 ms).
 template <int N, int NF>
-__global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
+__global__ __launch_bounds__((TraceShape<N, NF>::THREADS), 4) void k_sf_trace(
     const double* __restrict__ U, double* __restrict__ T2, SfOps sf, DevOps ops,
     const double* __restrict__ verts, int64_t K) {
   using D = SfDims<N>;
@@ -259,10 +263,27 @@ __global__ __launch_bounds__((TraceShape<N, NF>::THREADS)) void k_sf_trace(
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(K - e0 < E ? K - e0 : E);
-  for (int x = tid; x < ne * 4 * Np; x += NT) sU[x / (4 * Np)][x % (4 * Np)] = U[e0 * 4 * Np + x];
+  // The workgroup's state: every load of a thread issued before the first
+  // store (a compile-time count), so the loads overlap instead of each
+  // waiting out a memory round trip; the tables load meanwhile.
+  constexpr int ST = (E * 4 * Np + NT - 1) / NT;
+  const int nU = ne * 4 * Np;
+  const double* Ug = U + e0 * 4 * Np;
+  double ru[ST];
+#pragma unroll
+  for (int it = 0; it < ST; ++it) {
+    const int x = tid + it * NT;
+    ru[it] = x < nU ? Ug[x] : 0.0;
+  }
   for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
   for (int x = tid; x < D::n3; x += NT) sLa[x] = sf.La[x];
   for (int x = tid; x < 2 * n2; x += NT) sLe[x] = sf.Le[x];
+  double* sUf = &sU[0][0];
+#pragma unroll
+  for (int it = 0; it < ST; ++it) {
+    const int x = tid + it * NT;
+    if (x < nU) sUf[x] = ru[it];
+  }
   __syncthreads();
   for (int x = tid; x < ne * PTS; x += NT) {
     const int le = x / PTS, q = x % PTS;
