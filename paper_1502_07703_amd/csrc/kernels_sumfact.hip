@@ -342,10 +342,25 @@ __global__ __launch_bounds__((TraceAllShape<N>::THREADS)) void k_sf_trace_all(
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (int)(K - e0 < E ? K - e0 : E);
-  for (int x = tid; x < ne * 4 * Np; x += NT) sU[x / (4 * Np)][x % (4 * Np)] = U[e0 * 4 * Np + x];
+  // state loads all in flight before the LDS stores, as in k_sf_trace
+  constexpr int ST = (E * 4 * Np + NT - 1) / NT;
+  const int nU = ne * 4 * Np;
+  const double* Ug = U + e0 * 4 * Np;
+  double ru[ST];
+#pragma unroll
+  for (int it = 0; it < ST; ++it) {
+    const int x = tid + it * NT;
+    ru[it] = x < nU ? Ug[x] : 0.0;
+  }
   for (int x = tid; x < ne * 16; x += NT) sX[x / 16][x % 16] = verts[e0 * 16 + x];
   for (int x = tid; x < D::n3; x += NT) sLa[x] = sf.La[x];
   for (int x = tid; x < 2 * n2; x += NT) sLe[x] = sf.Le[x];
+  double* sUf = &sU[0][0];
+#pragma unroll
+  for (int it = 0; it < ST; ++it) {
+    const int x = tid + it * NT;
+    if (x < nU) sUf[x] = ru[it];
+  }
   for (int kj = tid; kj < KJ; kj += NT) {
     int k, j;
     kj_split<N>(kj, k, j);
